@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/paper_examples.json), closed forms (cofactors and
+minors, (3B-2)^d pair counts), identities (projected-tag cancellation,
+Atil = U* A V), exact recovery of planted exact-rank matrices, brute-force
+SVDs and brute-force scans of the aspect-ratio problem.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+from scipy.spatial.distance import cdist
+
+import oracle as O
+import workloads as W
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+def lattice_1d(b):
+    return np.arange(b, dtype=np.int32).reshape(b, 1)
+
+
+# ---------------------------------------------------------------- P1 lists/colours
+def test_p1_neighbour_example_1d():
+    ex = GOLDEN["neighbour_example_1d"]
+    near = O.near_lists(lattice_1d(ex["nboxes"]))
+    # paper numbers boxes from 1
+    assert [j + 1 for j in near[ex["box"] - 1]] == ex["neighbours"]
+    assert O.num_tag_columns(near, extra=0) == ex["tag_columns"]
+
+
+@pytest.mark.parametrize("dim,B", [(1, 9), (2, 8), (2, 5), (3, 4)])
+def test_p1_pair_counts_and_interior(dim, B):
+    g = W.grid_geometry(dim, B, 2)
+    near = O.near_lists(g.lattice)
+    assert sum(len(n) for n in near) == (3 * B - 2) ** dim
+    for i, n in enumerate(near):
+        interior = all(0 < g.lattice[i, t] < B - 1 for t in range(dim))
+        if interior:
+            assert len(n) == 3 ** dim
+        assert i in n and n == sorted(n)
+    far = O.far_lists(near, g.nboxes)
+    for i in range(g.nboxes):
+        assert sorted(near[i] + far[i]) == list(range(g.nboxes))
+
+
+@pytest.mark.parametrize("dim,B", [(1, 8), (2, 7), (3, 5)])
+def test_p1_colours_unique_per_neighbourhood(dim, B):
+    g = W.grid_geometry(dim, B, 1)
+    near = O.near_lists(g.lattice)
+    col = O.colours(g.lattice)
+    assert set(col.tolist()) == set(range(3 ** dim))
+    for n in near:
+        cs = [col[j] for j in n]
+        assert len(cs) == len(set(cs))
+
+
+def test_p1_probe_colour_example_1d():
+    ex = GOLDEN["probe_colour_example_1d"]
+    col = O.colours(lattice_1d(ex["nboxes"]))
+    members = [j + 1 for j in range(ex["nboxes"]) if col[j] == col[ex["boxes_in_one_colour"][0] - 1]]
+    assert members == ex["boxes_in_one_colour"]
+
+
+# ---------------------------------------------------------------- P2 null vectors
+def test_p2_cofactor_closed_form_and_minors():
+    """With ell = 3^d + 1 an interior box has a 1-D null space; z is proportional to
+    the signed cofactors of T(N_i,:) and T z lists the (ell x ell) determinants
+    [t_l; T(N_i,:)] (Section 5.2, eqs. cramers_rule and 4by4, with the
+    alternating signs that the cofactor expansion carries)."""
+    b = 8
+    near = O.near_lists(lattice_1d(b))
+    T = W.tag_matrix(7, b, 4)
+    i = 2
+    Ti = T[near[i]]
+    z = O.null_space(Ti)[:, 0]
+    cof = np.array([(-1) ** j * np.linalg.det(np.delete(Ti, j, axis=1)) for j in range(4)])
+    scale = cof @ z
+    assert np.allclose(z * scale, cof, rtol=0, atol=1e-13 * np.linalg.norm(cof))
+    minors = np.array([np.linalg.det(np.vstack([T[l], Ti])) for l in range(b)])
+    assert np.allclose(T @ cof, minors, rtol=0, atol=1e-12 * np.linalg.norm(minors))
+    assert np.linalg.norm(Ti @ z) <= 1e-14 * np.linalg.norm(T)
+    assert abs(np.linalg.norm(z) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("dim,B,extra", [(2, 6, 3), (3, 4, 3), (2, 5, 0)])
+def test_p2_tag_vectors_in_null_space(dim, B, extra):
+    g = W.grid_geometry(dim, B, 1)
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    ell = O.num_tag_columns(near, extra)
+    T = W.tag_matrix(11, g.nboxes, ell)
+    z, rho = O.tag_plan(T, near, far)
+    for i in range(g.nboxes):
+        assert np.linalg.norm(T[near[i]] @ z[i]) <= 1e-13 * np.linalg.norm(T)
+        assert abs(np.linalg.norm(z[i]) - 1) < 1e-13
+        assert rho[i] >= 1.0
+        assert np.isclose(rho[i], O.aspect_ratio(T, far[i], z[i]), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P10 worked example
+def test_p10_worked_example_zero_pattern():
+    """8 boxes in 1D, T is 8 x 4: the weighted sum of the Omega_j vanishes exactly on the
+    block rows of N_3 = {2,3,4} and nowhere else (eq. projected_tags)."""
+    b, m, r = 8, 5, 3
+    near = O.near_lists(lattice_1d(b))
+    far = O.far_lists(near, b)
+    T = W.tag_matrix(3, b, 4)
+    z, _ = O.optimise_tag_vector(T, near[2], far[2])
+    box_ptr = np.arange(b + 1) * m
+    G = W.gaussian_colmajor(3, 1, b * m, r)
+    Om = O.extended_test_matrix(T, G, box_ptr)
+    comb = sum(z[j] * Om[:, j * r:(j + 1) * r] for j in range(4))
+    for l in range(b):
+        blk = comb[l * m:(l + 1) * m]
+        if l + 1 in (2, 3, 4):
+            assert np.max(np.abs(blk)) < 1e-14
+        else:
+            assert np.max(np.abs(blk)) > 1e-6
+
+
+# ---------------------------------------------------------------- P3 cancellation
+def _small_dense_case(dim=2, B=5, q=3, k=4, p=3, seed=5):
+    g = W.grid_geometry(dim, B, q)
+    rs = np.random.default_rng(seed)
+    A = rs.standard_normal((g.n, g.n))
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(seed, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(seed, g.n, k + p)
+    return g, A, near, ell, T, G, H
+
+
+def test_p3_tag_cancellation_identity():
+    """Yhat_i = sum_{l in F_i} (T z^(i))_l A_il G_l and the A* analogue (eq. projected_tags):
+    near-field blocks drop out for any A, by brute force on a dense random matrix."""
+    k, p = 4, 3
+    g, A, near, ell, T, G, H = _small_dense_case(k=k, p=p)
+    r = k + p
+    far = O.far_lists(near, g.nboxes)
+    z, _ = O.tag_plan(T, near, far)
+    Y, Z = O.tagging.sketch(O.DenseOperator(A), T, G, H, g.box_ptr)
+    Yh = O.tag_postprocess(Y, z, g.box_ptr, r)
+    Zh = O.tag_postprocess(Z, z, g.box_ptr, r)
+    bp = g.box_ptr
+    for i in range(g.nboxes):
+        ri = slice(bp[i], bp[i + 1])
+        c = T @ z[i]
+        ref_y = sum(c[l] * A[ri, bp[l]:bp[l + 1]] @ G[bp[l]:bp[l + 1]] for l in far[i])
+        ref_z = sum(c[l] * A[bp[l]:bp[l + 1], ri].T @ H[bp[l]:bp[l + 1]] for l in far[i])
+        assert np.allclose(Yh[ri], ref_y, rtol=0, atol=1e-12 * np.abs(ref_y).max())
+        assert np.allclose(Zh[ri], ref_z, rtol=0, atol=1e-12 * np.abs(ref_z).max())
+
+
+# ---------------------------------------------------------------- P4 exact recovery
+@pytest.fixture(scope="module")
+def planted():
+    wl = W.WORKLOADS["planted_2d_n4096"]
+    g = wl.geometry()
+    A, us, vs = W.planted_exact_rank(g, wl.k, wl.seed)
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    op = O.CountingOperator(O.DenseOperator(A))
+    res = O.reconstruct_tag(op, g.box_ptr, g.lattice, wl.k, wl.p, 3, T, G, H)
+    return dict(wl=wl, g=g, A=A, us=us, vs=vs, res=res, op=op, ell=ell)
+
+
+def test_p4_planted_exact_recovery(planted):
+    g, A, res, k = planted["g"], planted["A"], planted["res"], planted["wl"].k
+    bp = g.box_ptr
+    Ubd = scipy.linalg.block_diag(*[res["U"][bp[i]:bp[i + 1]] for i in range(g.nboxes)])
+    Vbd = scipy.linalg.block_diag(*[res["V"][bp[i]:bp[i + 1]] for i in range(g.nboxes)])
+    Ah = Ubd @ res["Atil"] @ Vbd.T
+    for (i, j), Bij in res["B"].items():
+        Ah[bp[i]:bp[i + 1], bp[j]:bp[j + 1]] += Bij
+    assert np.linalg.norm(A - Ah) / np.linalg.norm(A) <= 1e-12
+    for i in range(g.nboxes):
+        Ui = res["U"][bp[i]:bp[i + 1]]
+        Vi = res["V"][bp[i]:bp[i + 1]]
+        assert np.linalg.norm(Ui @ Ui.T - planted["us"][i] @ planted["us"][i].T, 2) <= 1e-12
+        assert np.linalg.norm(Vi @ Vi.T - planted["vs"][i] @ planted["vs"][i].T, 2) <= 1e-12
+        assert np.allclose(Ui.T @ Ui, np.eye(k), atol=1e-13)
+
+
+def test_p6_cores_and_nearfield_vs_dense(planted):
+    """Atil_ij = U_i* A_ij V_j for all pairs and, for an exact-rank matrix (no far-field
+    leakage into the probes), B_ij = A_ij - U_i Atil_ij V_j* on neighbour pairs
+    (eq. uniformBLRbases ff., eq. discrepancymatrix), by dense slicing."""
+    g, A, res, k = planted["g"], planted["A"], planted["res"], planted["wl"].k
+    bp = g.box_ptr
+    U, V, At = res["U"], res["V"], res["Atil"]
+    for i in range(0, g.nboxes, 5):
+        for j in range(g.nboxes):
+            blk = U[bp[i]:bp[i + 1]].T @ A[bp[i]:bp[i + 1], bp[j]:bp[j + 1]] @ V[bp[j]:bp[j + 1]]
+            assert np.allclose(At[i * k:(i + 1) * k, j * k:(j + 1) * k], blk, atol=1e-12)
+    assert set(res["B"].keys()) == {(i, j) for i in range(g.nboxes) for j in res["near"][i]}
+    for (i, j), Bij in res["B"].items():
+        ref = A[bp[i]:bp[i + 1], bp[j]:bp[j + 1]] - \
+            U[bp[i]:bp[i + 1]] @ At[i * k:(i + 1) * k, j * k:(j + 1) * k] @ V[bp[j]:bp[j + 1]].T
+        assert np.allclose(Bij, ref, atol=1e-12)
+
+
+def test_p6_apply_equals_matrix_for_exact_rank(planted):
+    g, A, res, k = planted["g"], planted["A"], planted["res"], planted["wl"].k
+    x = np.random.default_rng(0).standard_normal((g.n, 3))
+    y = O.ublr_apply(res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k, x)
+    yt = O.ublr_apply(res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k, x, trans=True)
+    assert np.allclose(y, A @ x, atol=1e-11 * np.abs(A @ x).max())
+    assert np.allclose(yt, A.T @ x, atol=1e-11 * np.abs(A.T @ x).max())
+
+
+# ---------------------------------------------------------------- P7 matvec counts
+def test_p7_matvec_counts(planted):
+    """Sketch 2 ell r products (Section 4.2), cores bk and near field 3^d m (Table 1)."""
+    g, wl, op = planted["g"], planted["wl"], planted["op"]
+    ell, r, k = planted["ell"], wl.r, wl.k
+    m = int(np.max(g.box_sizes()))
+    assert op.cols_At == ell * r
+    assert op.cols_A == ell * r + g.nboxes * k + 3 ** g.dim * m
+
+
+# ---------------------------------------------------------------- P8 sizing rule
+def test_p8_block_count_rule():
+    ex = GOLDEN["block_count_rule"]
+    for c in ex["cases"]:
+        assert W.blocks_for_rank(c["N"], ex["k"], ex["dim"]) == c["b"]
+
+
+# ---------------------------------------------------------------- P5 bases
+def test_p5_bases_vs_bruteforce_svd():
+    """On a small Laplace problem the basis captures the far-field block row nearly as
+    well as its optimal rank-k subspace: ||(I - U U*) A(I_i, F_i)||_2 is within a
+    modest factor (times the aspect ratio) of sigma_{k+1} plus the tail
+    (randomized range finder guarantee, Section 2.4)."""
+    g = W.grid_geometry(2, 6, 4)          # 36 boxes of 16 points
+    k, p = 4, 6
+    op = O.KernelOperator("log", g.pts)
+    A = op.block()
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(21, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(21, g.n, k + p)
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, k, p, 3, T, G, H,
+                            steps=("I",))
+    bp = g.box_ptr
+    for i in range(g.nboxes):
+        ri = slice(bp[i], bp[i + 1])
+        cols = np.concatenate([np.arange(bp[l], bp[l + 1]) for l in res["far"][i]])
+        Ai = A[ri][:, cols]
+        s = np.linalg.svd(Ai, compute_uv=False)
+        U = res["U"][ri]
+        err = np.linalg.norm(Ai - U @ (U.T @ Ai), 2)
+        tail = np.sqrt(np.sum(s[k:] ** 2))
+        assert err <= 10 * res["rho"][i] * tail + 1e-13 * np.abs(A).max()
+        assert err >= s[k] * (1 - 1e-10)            # no rank-k basis beats the SVD
+        # V from the adjoint side, against the far-field block column
+        Vi = res["V"][ri]
+        Ac = A[cols][:, ri]
+        sc = np.linalg.svd(Ac, compute_uv=False)
+        errv = np.linalg.norm(Ac - (Ac @ Vi) @ Vi.T, 2)
+        assert errv <= 10 * res["rho"][i] * np.sqrt(np.sum(sc[k:] ** 2)) + 1e-13 * np.abs(A).max()
+
+
+def test_col_topk_matches_known_subspace():
+    rs = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(rs.standard_normal((30, 5)))
+    M = Q @ np.diag([5, 4, 3, 2, 1.0]) @ rs.standard_normal((5, 9))
+    U = O.col_topk(M, 5)
+    assert np.linalg.norm(U @ U.T - Q @ Q.T, 2) < 1e-13
+    for c in range(5):
+        assert U[np.argmax(np.abs(U[:, c])), c] > 0
+
+
+# ---------------------------------------------------------------- aspect-ratio LP
+def test_lp_improves_on_every_start():
+    g = W.grid_geometry(2, 6, 1)
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(5, g.nboxes, ell)
+    for i in range(g.nboxes):
+        z, rho = O.optimise_tag_vector(T, near[i], far[i], optimise=True)
+        z0, rho0 = O.optimise_tag_vector(T, near[i], far[i], optimise=False)
+        assert rho <= rho0 * (1 + 1e-12)
+        X = O.null_space(T[near[i]])
+        P = X @ X.T
+        for j in range(ell):
+            w = P[:, j]
+            if np.linalg.norm(w) > 1e-12:
+                assert rho <= O.aspect_ratio(T, far[i], w) * (1 + 1e-9)
+
+
+def test_lp_cell_optimum_matches_bruteforce_scan_2d_nullspace():
+    """With a 2-D null space the unit vectors are a circle; scanning it finely and
+    refining locally gives the minimum aspect ratio in each sign cell, which must
+    equal the LP optimum for the cell that the LP picked."""
+    b = 12
+    near = O.near_lists(lattice_1d(b))
+    far = O.far_lists(near, b)
+    T = W.tag_matrix(9, b, 5)              # ell = 3 + 2: interior null space is 2-D
+    i = 5
+    X = O.null_space(T[near[i]])
+    assert X.shape[1] == 2
+    z, rho = O.optimise_tag_vector(T, near[i], far[i])
+    Tf = T[far[i]]
+    sig = np.sign(Tf @ z)
+    th = np.linspace(0, 2 * np.pi, 200001)
+    pts = np.cos(th)[:, None] * X[:, 0] + np.sin(th)[:, None] * X[:, 1]
+    c = pts @ Tf.T
+    same = np.all(np.sign(c) == sig, axis=1)
+    ratios = np.where(same, np.max(np.abs(c), axis=1) / np.min(np.abs(c), axis=1), np.inf)
+    j = int(np.argmin(ratios))
+    lo, hi = th[max(j - 1, 0)], th[min(j + 1, th.size - 1)]
+    from scipy.optimize import minimize_scalar
+    f = lambda t: (lambda v: np.max(np.abs(v)) / np.min(np.abs(v)))(Tf @ (np.cos(t) * X[:, 0] + np.sin(t) * X[:, 1]))
+    best = minimize_scalar(f, bounds=(lo, hi), method="bounded", options={"xatol": 1e-13}).fun
+    assert abs(best - rho) <= 1e-7 * rho
+
+
+# ---------------------------------------------------------------- kernels, errors
+@pytest.mark.parametrize("kind", ["log", "inv_r", "exp", "cos"])
+def test_kernel_blocks_vs_cdist(kind):
+    g = W.grid_geometry(2, 3, 4, jitter=0.25, seed=3)
+    op = O.KernelOperator(kind, g.pts)
+    A = op.block()
+    d = cdist(g.pts, g.pts)
+    np.fill_diagonal(d, 1.0)
+    ref = {"log": np.log(d), "inv_r": 1 / d, "exp": np.exp(-d / 0.1),
+           "cos": np.cos(20 * d) / (d + 1e-3)}[kind]
+    np.fill_diagonal(ref, {"log": 0.0, "inv_r": 0.0, "exp": 1.0, "cos": 1000.0}[kind])
+    assert np.allclose(A, ref, rtol=1e-14, atol=1e-14)
+    assert np.allclose(A, A.T, rtol=0, atol=0)
+    x = np.random.default_rng(2).standard_normal((g.n, 2))
+    assert np.allclose(op.matmat(x), ref @ x, atol=1e-12 * np.abs(ref @ x).max())
+
+
+def test_p9_errors_fro_and_power():
+    """Exact Frobenius error matches a dense computation; the 20-step power estimate of
+    ||A - A_uBLR||_2 is a lower bound within 10% of the dense 2-norm."""
+    g = W.grid_geometry(2, 6, 4)
+    k, p = 3, 5
+    op = O.KernelOperator("log", g.pts)
+    A = op.block()
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(4, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(4, g.n, k + p)
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, k, p, 3, T, G, H)
+    bp = g.box_ptr
+    Ubd = scipy.linalg.block_diag(*[res["U"][bp[i]:bp[i + 1]] for i in range(g.nboxes)])
+    Vbd = scipy.linalg.block_diag(*[res["V"][bp[i]:bp[i + 1]] for i in range(g.nboxes)])
+    Ah = Ubd @ res["Atil"] @ Vbd.T
+    for (i, j), Bij in res["B"].items():
+        Ah[bp[i]:bp[i + 1], bp[j]:bp[j + 1]] += Bij
+    E = A - Ah
+    fro = O.rel_fro_error(op, res["U"], res["V"], res["Atil"], res["B"], bp, k)
+    assert np.isclose(fro, np.linalg.norm(E) / np.linalg.norm(A), rtol=1e-10)
+    x0 = W.gaussian_colmajor(4, W.STREAM_POWER, g.n, 1)[:, 0]
+    est = O.power_norm_estimate(lambda v: E @ v, lambda v: E.T @ v, g.n, x0, 20)
+    true = np.linalg.norm(E, 2)
+    assert est <= true * (1 + 1e-12) and est >= 0.9 * true
