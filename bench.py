@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark: tagged uniform-BLR compression (reconstruct_tag) on one MI355X.
+
+A step is one full compression -- tagged sketches, tag post-processing,
+per-box bases, cores and near field -- of a synthetic kernel matrix whose
+inputs (points, T, G, H) are resident in HBM before timing starts.  The
+default workload is the 2D Laplace kernel log|x - y| on a 256 x 256 grid
+(N = 65536), 16 x 16 boxes of 256 points, k = 32, p = 10, ell = 13, FP64.
+
+Prints one JSON line with the driver's fields plus the roofline of the
+dominant kernel (the sketch, FP64 MFMA) and a CPU baseline (the FP64 oracle
+timed on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "BLR compressions/s + operator-applies per compression at 1e-8 rel err; %MFMA/HBM"
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def setup(wl_name):
+    import torch
+    import paper_2501_05528_amd as P
+    wl = W.WORKLOADS[wl_name]
+    g = wl.geometry()
+    ell = P.tag_columns(g.box_ptr, g.lattice, wl.extra_tag_cols)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    t0 = time.perf_counter()
+    plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=wl.extra_tag_cols)
+    plan_s = time.perf_counter() - t0
+    op = P.Operator.kernel(wl.kind, g.pts)
+    Gd, Hd = P.colmajor(G), P.colmajor(H)
+    torch.cuda.synchronize()
+    return dict(wl=wl, g=g, T=T, G=G, H=H, plan=plan, op=op, Gd=Gd, Hd=Hd, plan_s=plan_s, P=P)
+
+
+def cpu_baseline(S, nsample_boxes=4):
+    """The oracle, as it stands, on a bounded sample: every stage of reconstruct_tag
+    restricted to `nsample_boxes` row boxes (sketch rows, their post-processing and
+    bases, their rows of the cores and of the near-field probes), extrapolated to
+    all b row boxes.  The column-side bases V (all boxes) are part of the sample
+    cost only through the rows sampled here, which is what the oracle's sketch
+    costs per row; the extrapolation is linear in the number of row boxes."""
+    import oracle as O
+    wl, g = S["wl"], S["g"]
+    k, r = wl.k, wl.r
+    bp = g.box_ptr
+    boxes = list(range(0, g.nboxes, max(1, g.nboxes // nsample_boxes)))[:nsample_boxes]
+    rows = np.concatenate([np.arange(bp[i], bp[i + 1]) for i in boxes])
+    sub_ptr = np.concatenate([[0], np.cumsum([bp[i + 1] - bp[i] for i in boxes])])
+    op = O.KernelOperator(wl.kind, g.pts)
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    col = O.colours(g.lattice)
+    T = S["T"]
+    t0 = time.perf_counter()
+    zs = np.zeros((len(boxes), T.shape[1]))
+    for q, i in enumerate(boxes):
+        zs[q], _ = O.optimise_tag_vector(T, near[i], far[i])
+    Om = O.extended_test_matrix(T, S["G"], bp)
+    Ps = O.extended_test_matrix(T, S["H"], bp)
+    Y = op.matmat(Om, rows=rows)
+    Z = op.rmatmat(Ps, rows=rows)
+    Yh = O.tag_postprocess(Y, zs, sub_ptr, r)
+    Zh = O.tag_postprocess(Z, zs, sub_ptr, r)
+    U, V = O.tag_bases(Yh, Zh, sub_ptr, k)
+    # cores rows U_i* (A V)(I_i, :) with V = diag(V_j): bk products restricted to the rows
+    Vfull = np.zeros((g.n, k))
+    for q, i in enumerate(boxes):
+        Vfull[bp[i]:bp[i + 1]] = V[sub_ptr[q]:sub_ptr[q + 1]]
+    Vbd = O.reconstruct._blockdiag(Vfull, bp, k)
+    W_rows = op.matmat(Vbd, rows=rows)
+    At_rows = [U[sub_ptr[q]:sub_ptr[q + 1]].T @ W_rows[sub_ptr[q]:sub_ptr[q + 1]] for q in range(len(boxes))]
+    # near-field probe rows: (A X_c)(I_i, :) for every colour
+    mmax = int(np.max(g.box_sizes()))
+    for c in range(3 ** g.dim):
+        X = np.zeros((g.n, mmax))
+        for l in range(g.nboxes):
+            if col[l] == c:
+                X[bp[l]:bp[l + 1], :bp[l + 1] - bp[l]] = np.eye(bp[l + 1] - bp[l])
+        _ = op.matmat(X, rows=rows)
+    dt = time.perf_counter() - t0
+    del At_rows
+    per_comp = dt * g.nboxes / len(boxes)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(d.get("num_threads", threads)) for d in info)
+    except Exception:
+        pass
+    return {"value": 1.0 / per_comp, "unit": "compressions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(boxes)} of {g.nboxes} row boxes of every stage "
+                      f"({dt:.1f} s), extrapolated linearly to all row boxes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="laplace2d_n65536")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   "multi-GPU sharding is not part of this build"}))
+        sys.exit(2)
+    import torch
+    log(f"setup {args.workload}")
+    S = setup(args.workload)
+    P, plan, op = S["P"], S["plan"], S["op"]
+    wl, g = S["wl"], S["g"]
+    for w in range(args.warmup):
+        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True)
+        log(f"warmup {w}: {rep['ms_total']:.1f} ms (sketch {rep['ms_sketch']:.1f})")
+        del h
+    torch.cuda.synchronize()
+    handles, reps = [], []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True)
+        handles.append(h)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    last = handles[-1]
+    err_fro = None
+    if not args.no_error:
+        err_fro = last.error_fro(op)
+        log(f"relative Frobenius error {err_fro:.3e}")
+    del handles
+    ms_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+    stage = {k: float(np.mean([r[k] for r in reps])) for k in
+             ("ms_sketch", "ms_postprocess", "ms_orth", "ms_cores", "ms_nearfield", "ms_total")}
+    applies = int(reps[0]["applies_A"] + reps[0]["applies_At"])
+    sketch_flops = reps[0]["sketch_flops"]
+    achieved = sketch_flops / (stage["ms_sketch"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "k_opgemm (tagged sketch, FP64 MFMA)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "algorithmic_flops_per_launch": sketch_flops}
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "kernel": wl.kind, "N": g.n, "boxes": g.nboxes,
+                   "m": int(np.max(g.box_sizes())), "k": wl.k, "p": wl.p, "ell": plan.ell,
+                   "precision": "fp64"},
+        "applies_per_compression": applies,
+        "applies_per_s": round(applies * value, 1),
+        "rel_err_fro": err_fro,
+        "stage_ms": {k: round(v, 3) for k, v in stage.items()},
+        "plan_s": round(S["plan_s"], 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(S)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,307 @@
+/*
+ * blr_tag.h -- C ABI of the MI355X (gfx950) library for black-box compression
+ * of strongly admissible uniform Block Low-Rank (uBLR) matrices by tagging.
+ *
+ * Method: Pearce, Yesypenko, Levitt, Martinsson, "Randomized Block Low-Rank
+ * Matrix Compression by Tagging" (arXiv 2501.05528).  The operator A is known
+ * only through products X -> A X and X -> A* X (Section 1).  Compression
+ * follows Table 1, column reconstruct_tag:
+ *   (I)  [U, V] = tag(A, A*, k)           Alg. 2 (sketch, tag post-processing, col)
+ *   (II) Atil = U* (A V)                  bk products
+ *   (III) B from 3^d sparse identity probes (eq. sparse_struct_ids)
+ * giving A ~ U Atil V* + B (eq. uniformBLRfull, eq. discrepancymatrix).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Status: every function returns blr_status; BLR_OK is 0.  On error the
+ *    out-pointers are set to NULL, nothing is leaked, and
+ *    blr_last_error_message() (thread-local) describes the failure.  No C++
+ *    exception crosses the ABI.
+ *  * Memory: "host" pointers are ordinary CPU memory read synchronously
+ *    during the call; "device" pointers are HIP device memory on the device
+ *    current at the call.  The caller owns every pointer it passes; the
+ *    library owns the objects it creates (plan, operator, ublr) until the
+ *    matching destroy call.
+ *  * Layouts: matrices are column-major FP64 with the given leading
+ *    dimension unless stated.  Rows are in box-major order: box i owns rows
+ *    [box_ptr[i], box_ptr[i+1]).
+ *  * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Device work is enqueued asynchronously on it; results are
+ *    valid once the stream has been synchronised.  Arguments are validated
+ *    synchronously before anything is enqueued.
+ */
+#ifndef BLR_TAG_H
+#define BLR_TAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum blr_status {
+    BLR_OK = 0,
+    BLR_ERR_INVALID_ARG = 1, /* bad sizes/pointers, k + p > min m_i, wrong T shape ... */
+    BLR_ERR_GEOMETRY = 2,    /* some box has an empty far field, or T(N_i,:) is rank deficient */
+    BLR_ERR_OOM = 3,         /* device or host allocation failed */
+    BLR_ERR_DEVICE = 4,      /* a HIP runtime call failed */
+    BLR_ERR_OPERATOR = 5,    /* a user operator callback returned nonzero */
+    BLR_ERR_NUMERICAL = 6,   /* non-finite sketch or basis */
+    BLR_ERR_BUSY = 7,        /* server admission refused (over budget) */
+    BLR_ERR_UNSUPPORTED = 8  /* combination not implemented (e.g. precision for this operator) */
+} blr_status;
+
+typedef struct blr_plan blr_plan;
+typedef struct blr_operator blr_operator;
+typedef struct blr_ublr blr_ublr;
+
+/* Human-readable name of a status code (static storage). */
+const char* blr_status_string(blr_status s);
+/* Message of the last failed call on this thread (empty if none). */
+const char* blr_last_error_message(void);
+/* Library version string. */
+const char* blr_version(void);
+
+/* ------------------------------------------------------------------ plan
+ * Geometry of the tessellation (Section 2.5): b boxes with index sets I_i
+ * and their integer coordinates on a d-dimensional box lattice.  Strong
+ * admissibility: the neighbours N_i of box i are the boxes at lattice
+ * Chebyshev distance <= 1 (those sharing a boundary, i included; at most
+ * 3^d), the far field is F_i = [b] \ N_i.
+ */
+typedef struct blr_geometry {
+    int32_t dim;                /* d in {1, 2, 3} */
+    int32_t nboxes;             /* b >= 2 */
+    const int64_t* box_ptr;     /* host, b+1 entries, box_ptr[0] = 0, strictly increasing */
+    const int32_t* box_lattice; /* host, b*dim entries, box i at [i*dim, i*dim+dim) */
+} blr_geometry;
+
+/*
+ * Number of columns ell of the tagging matrix T for a geometry: one more
+ * than the largest neighbour count (Section 4.1) plus `extra_tag_cols`
+ * additional columns that give every tag submatrix a null space of
+ * dimension >= extra_tag_cols + 1 (Section 5.3; the paper's experiments use
+ * 3 additional columns, Section 7).  Host only.
+ */
+blr_status blr_tag_columns(const blr_geometry* geom, int32_t extra_tag_cols, int32_t* ell_out);
+
+typedef struct blr_tag_params {
+    int32_t k;              /* block rank, >= 1 */
+    int32_t p;              /* oversampling, r = k + p; requires r <= min_i m_i */
+    int32_t extra_tag_cols; /* >= 0; ell = max|N_i| + 1 + extra_tag_cols */
+    int32_t aspect_opt;     /* 1: minimise the aspect ratio (Section 5.3, LP per sign cell);
+                               0: use the projection of the first start vector */
+    const double* T;        /* host, b x ell column-major Gaussian tagging matrix (Alg. 2);
+                               the caller draws it so results are reproducible */
+} blr_tag_params;
+
+/*
+ * Build a compression plan (host only, no device calls): neighbour and far
+ * lists, probe colours, and for every box the unit tag vector
+ * z^(i) in null(T(N_i,:)) (Alg. 2; eq. tagsubmat) chosen to minimise the
+ * aspect ratio rho^(i) of its projected tags (eq. aspect_ratio).  The plan is
+ * immutable, reusable across operators, streams and threads, and uploads its
+ * device tables lazily on first use per device.
+ * Errors: BLR_ERR_INVALID_ARG (shapes, k + p > min m_i, NULL T),
+ *         BLR_ERR_GEOMETRY (empty far field, rank-deficient T(N_i,:)).
+ */
+blr_status blr_tag_plan(const blr_geometry* geom, const blr_tag_params* params, blr_plan** out);
+void blr_plan_destroy(blr_plan* plan);
+
+typedef struct blr_plan_info {
+    int64_t n;          /* N = box_ptr[b] */
+    int32_t nboxes;     /* b */
+    int32_t dim;        /* d */
+    int32_t k, p, r;    /* rank, oversampling, r = k + p */
+    int32_t ell;        /* columns of T */
+    int32_t m_max;      /* largest box */
+    int32_t m_min;      /* smallest box */
+    int32_t ncolours;   /* 3^d probe colours */
+    int64_t near_nnz;   /* number of neighbour pairs (i, j in N_i) */
+    int64_t b_values;   /* doubles needed for all near-field blocks of B */
+} blr_plan_info;
+
+blr_status blr_plan_query(const blr_plan* plan, blr_plan_info* info);
+
+/*
+ * Copy the plan's lists to host arrays (any pointer may be NULL to skip it).
+ *   near_ptr [b+1], near_idx [near_nnz]: CSR of N_i, ascending, self included
+ *   colour   [b]: probe colour sum_t (lat_t mod 3) 3^t
+ *   b_offset [near_nnz]: offset (in doubles) of block B_ij in the B value
+ *            array; block (i, j) is m_i x m_j column-major, pairs in CSR order
+ */
+blr_status blr_plan_lists(const blr_plan* plan, int32_t* near_ptr, int32_t* near_idx,
+                          int32_t* colour, int64_t* b_offset);
+
+/* Copy tag vectors z (b x ell, column-major) and aspect ratios rho [b] to host. */
+blr_status blr_plan_tags(const blr_plan* plan, double* z, double* rho);
+
+/* ------------------------------------------------------------- operators
+ * The black box A (N x N).  Built-in operators are evaluated by fused HIP
+ * kernels that never form A (kernel matrices) or read it in place (dense).
+ */
+typedef enum blr_kernel_kind {
+    BLR_KERNEL_LOG = 0,   /* log|x - y|, diagonal 0 (Section 7.1) */
+    BLR_KERNEL_INV_R = 1, /* 1/|x - y|, diagonal 0 */
+    BLR_KERNEL_EXP = 2,   /* exp(-|x - y| / 0.1), diagonal 1 */
+    BLR_KERNEL_COS = 3    /* cos(20|x - y|) / (|x - y| + 1e-3), diagonal 1000 */
+} blr_kernel_kind;
+
+/*
+ * Dense operator: A is device memory, n x n column-major with leading
+ * dimension lda >= n, borrowed (must outlive the operator and every call
+ * that uses it).  A* products read A transposed in place.
+ */
+blr_status blr_op_dense_create(int64_t n, const double* A, int64_t lda, blr_operator** out);
+
+/*
+ * Kernel-matrix operator A_ij = kappa(|x_i - x_j|) (A_ii = the diagonal
+ * value), evaluated on the fly.  pts is host memory, n x dim row-major
+ * (point i at pts[i*dim ...]); the library keeps its own device copy.
+ * The matrix is symmetric, so A* = A.
+ */
+blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const double* pts,
+                                blr_operator** out);
+void blr_op_destroy(blr_operator* op);
+
+/*
+ * Y = A X (trans = 0) or Y = A* X (trans = 1) for X (n x ncols, device,
+ * ldx >= n) into Y (n x ncols, device, ldy >= n).  The operator's own
+ * black-box product, exposed for error estimation and testing.
+ */
+blr_status blr_op_apply(const blr_operator* op, int32_t trans, int64_t ncols, const double* X,
+                        int64_t ldx, double* Y, int64_t ldy, void* stream);
+
+/* ------------------------------------------------------- compression stages
+ * Stage entry points of reconstruct_tag; blr_tag_compress chains them.  All
+ * arrays are device memory, column-major with leading dimension N.
+ */
+
+/*
+ * Tagged sketches (Alg. 2, sketch step; eq. extend_test_mat): Y = A Omega
+ * and Z = A* Psi, each N x (ell*r), where block column j of Omega has block
+ * row i equal to T(i,j) G_i (G: N x r stacked G_i) and Psi likewise from H
+ * with the same T.  Omega and Psi are formed inside the kernel and never
+ * stored.  Y, Z: N x ell*r, leading dimension N.
+ */
+blr_status blr_sketch(const blr_plan* plan, const blr_operator* op, const double* G,
+                      const double* H, double* Y, double* Z, void* stream);
+
+/*
+ * Tag post-processing (Alg. 2, loop over boxes; eq. projected_tags):
+ * Yhat(I_i,:) = sum_j z^(i)_j Y(I_i, (j-1)r+1 : jr), which cancels every
+ * near-field contribution, and Zhat likewise from Z.  Yhat, Zhat: N x r.
+ * Y or Yhat (Z or Zhat) may be NULL to skip that side.
+ */
+blr_status blr_tag_postprocess(const blr_plan* plan, const double* Y, const double* Z,
+                               double* Yhat, double* Zhat, void* stream);
+
+/*
+ * Per-box bases (Alg. 2, U_i = col(Yhat(I_i,:), k); Section 2.3): the k
+ * dominant left singular vectors of each m_i x r block of S, by batched
+ * one-sided Jacobi in FP64, sorted by singular value, each column signed so
+ * that its entry of largest magnitude is positive.  S is overwritten
+ * (scratch).  Q: N x k output.  sigma: optional device array b x r of the
+ * block singular values (descending), or NULL.
+ */
+blr_status blr_orthonormalize(const blr_plan* plan, double* S, double* Q, double* sigma,
+                              void* stream);
+
+/*
+ * Cores (Table 1 step 2): Atil = U* (A V) with U = diag(U_i), V = diag(V_j),
+ * i.e. Atil_ij = U_i* A_ij V_j for every pair (far pairs are the cores
+ * S_ij of eq. uniformBLRblock; near pairs feed step III).  Atil: bk x bk
+ * column-major (leading dimension b*k).
+ */
+blr_status blr_cores(const blr_plan* plan, const blr_operator* op, const double* U,
+                     const double* V, double* Atil, void* stream);
+
+/*
+ * Near-field remainder (Table 1 step 3; eq. sparse_struct_ids): for every
+ * colour c the probe P_c = (A - U Atil V*) X_c with X_c the identity blocks
+ * on the boxes of colour c, and B_il = P_c(I_i, 1:m_l) for the neighbour l
+ * of box i of colour c.  Bvals: b_values doubles laid out by b_offset.
+ */
+blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const double* U,
+                         const double* V, const double* Atil, double* Bvals, void* stream);
+
+/* ------------------------------------------------------------ compression */
+typedef enum blr_precision {
+    BLR_PREC_FP64 = 0 /* every stage in FP64 */
+} blr_precision;
+
+typedef struct blr_compress_opts {
+    int32_t precision;          /* blr_precision */
+    int32_t keep_intermediates; /* 1: keep Y, Z, Yhat, Zhat in the handle for inspection */
+} blr_compress_opts;
+
+typedef struct blr_report {
+    /* stage times (ms, device events on the stream) */
+    double ms_sketch, ms_postprocess, ms_orth, ms_cores, ms_nearfield, ms_total;
+    /* products in the paper's convention (columns applied to A and to A*) */
+    int64_t applies_A, applies_At;
+    /* algorithmic work of the sketch launch */
+    double sketch_flops;
+    /* aspect ratios of the plan */
+    double rho_min, rho_median, rho_max;
+} blr_report;
+
+/*
+ * Full compression reconstruct_tag (Table 1): steps (I)-(III).  G and H
+ * (device, N x r column-major, ld N) are the stacked Gaussian blocks G_i,
+ * H_i of Alg. 2 drawn by the caller.  opts may be NULL (FP64, no
+ * intermediates).  On success *out owns device U, V (N x k), Atil
+ * (bk x bk) and B (b_values doubles); it keeps a reference to the plan.
+ * If rep is non-NULL the call synchronises the stream and fills it.
+ */
+blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
+                            const double* H, const blr_compress_opts* opts, void* stream,
+                            blr_ublr** out, blr_report* rep);
+void blr_ublr_destroy(blr_ublr* h);
+
+/* Which device array of a compressed handle. */
+typedef enum blr_ublr_part {
+    BLR_PART_U = 0,     /* N x k */
+    BLR_PART_V = 1,     /* N x k */
+    BLR_PART_ATIL = 2,  /* bk x bk */
+    BLR_PART_B = 3,     /* b_values */
+    BLR_PART_Y = 4,     /* N x ell r   (keep_intermediates only) */
+    BLR_PART_Z = 5,     /* N x ell r   (keep_intermediates only) */
+    BLR_PART_YHAT = 6,  /* N x r       (keep_intermediates only) */
+    BLR_PART_ZHAT = 7   /* N x r       (keep_intermediates only) */
+} blr_ublr_part;
+
+/* Device pointer and element count of one part (the handle keeps ownership). */
+blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const double** ptr, int64_t* count);
+
+/*
+ * y = A_uBLR x = U (Atil (V* x)) + B x (trans = 0) or A_uBLR* x (trans = 1)
+ * (eq. uniformBLRfull), x: N x ncols device (ldx >= N), y: N x ncols device
+ * (ldy >= N).  Uses library-owned workspace in the handle, so calls on one
+ * handle must not overlap in time on different streams.
+ */
+blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x, int64_t ldx,
+                     double* y, int64_t ldy, void* stream);
+
+/*
+ * Exact relative Frobenius error ||A - A_uBLR||_F / ||A||_F of a built-in
+ * operator, block by block with entry access (evaluation harness; not part
+ * of the black-box method).  Synchronises the stream.
+ */
+blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream, double* rel_err);
+
+/*
+ * The paper's accuracy metric (Section 7): ||A - A_uBLR||_2 / ||A||_2, each
+ * norm by `iters` power iterations on M* M started from the given unit-norm
+ * device vector x0 (N).  Only operator and uBLR products are used.
+ * Synchronises the stream.  Outputs may be NULL.
+ */
+blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const double* x0,
+                           int32_t iters, void* stream, double* err_norm, double* a_norm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLR_TAG_H */

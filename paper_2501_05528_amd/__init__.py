@@ -1,0 +1,13 @@
+"""MI355X-native (gfx950) black-box compression of strongly admissible uniform
+Block Low-Rank matrices by tagging (Pearce, Yesypenko, Levitt, Martinsson,
+arXiv 2501.05528).
+
+The compute path is the HIP library ``libblrtag.so`` (C ABI in
+``include/blr_tag.h``); this package is its thin binding.  Build the library
+with ``python -m paper_2501_05528_amd.build``.
+"""
+from .api import (BlrError, Operator, Plan, UBLR, colmajor, colmajor_empty, compress,  # noqa: F401
+                  cores, nearfield, orthonormalize, postprocess, sketch, tag_columns)
+
+__all__ = ["BlrError", "Operator", "Plan", "UBLR", "colmajor", "colmajor_empty", "compress",
+           "cores", "nearfield", "orthonormalize", "postprocess", "sketch", "tag_columns"]

@@ -1,0 +1,271 @@
+"""Thin Python binding over the C ABI (argument marshalling only).
+
+Device matrices are torch CUDA float64 tensors of shape (rows, cols) in
+column-major layout (strides (1, rows)); ``colmajor`` builds them.  Every
+computation runs in the HIP library; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+from . import _lib
+from ._lib import BlrError, check, lib  # noqa: F401
+
+KERNELS = {"log": 0, "inv_r": 1, "exp": 2, "cos": 3}
+PARTS = {"U": 0, "V": 1, "Atil": 2, "B": 3, "Y": 4, "Z": 5, "Yhat": 6, "Zhat": 7}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor_empty(rows: int, cols: int, device=None):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=torch.float64, device=device or "cuda").t()
+
+
+def colmajor(a, device=None):
+    """Copy a 2-D array (numpy or torch) to a column-major CUDA float64 tensor."""
+    torch = _torch()
+    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    if t.dim() == 1:
+        t = t[:, None]
+    out = colmajor_empty(t.shape[0], t.shape[1], device)
+    out.copy_(t.to(torch.float64))
+    return out
+
+
+class _DeviceView:
+    """Column-major (rows x cols) float64 device memory owned by the library."""
+
+    def __init__(self, ptr: int, rows: int, cols: int):
+        self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": "<f8",
+                                         "data": (ptr, False), "version": 2,
+                                         "strides": (8, 8 * rows)}
+
+
+def colmajor_copy(t):
+    out = colmajor_empty(t.shape[0], t.shape[1], t.device)
+    out.copy_(t)
+    return out
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def _ld(t):
+    """Leading dimension of a column-major (rows, cols) tensor."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.stride(0) != 1 and t.shape[1] > 1:
+        raise ValueError("expected a column-major tensor (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0]) if t.shape[1] > 1 else t.shape[0]
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _geometry(box_ptr, lattice):
+    bp = np.ascontiguousarray(box_ptr, dtype=np.int64)
+    lat = np.ascontiguousarray(lattice, dtype=np.int32)
+    g = _lib.Geometry(lat.shape[1], lat.shape[0], bp.ctypes.data_as(_lib.P_i64),
+                      lat.ctypes.data_as(_lib.P_i32))
+    return g, (bp, lat)
+
+
+def tag_columns(box_ptr, lattice, extra_tag_cols: int = 3) -> int:
+    g, keep = _geometry(box_ptr, lattice)
+    ell = c_int32()
+    check(lib().blr_tag_columns(byref(g), extra_tag_cols, byref(ell)))
+    return ell.value
+
+
+class Plan:
+    """Host plan: lists, colours, tag vectors z and aspect ratios rho."""
+
+    def __init__(self, box_ptr, lattice, k: int, T, p: int = 10, extra_tag_cols: int = 3,
+                 aspect_opt: bool = True):
+        g, keep = _geometry(box_ptr, lattice)
+        Tf = np.asfortranarray(T, dtype=np.float64)
+        prm = _lib.TagParams(k, p, extra_tag_cols, 1 if aspect_opt else 0,
+                             Tf.ctypes.data_as(_lib.P_f64))
+        h = c_void_p()
+        ell = tag_columns(box_ptr, lattice, extra_tag_cols)
+        if Tf.shape != (g.nboxes, ell):
+            raise ValueError(f"T must be {g.nboxes} x {ell}, got {Tf.shape}")
+        check(lib().blr_tag_plan(byref(g), byref(prm), byref(h)))
+        self._h = h
+        info = _lib.PlanInfo()
+        check(lib().blr_plan_query(h, byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _lib.PlanInfo._fields_}
+        self.n = info.n
+        self.b = info.nboxes
+        self.k, self.r, self.ell = info.k, info.r, info.ell
+
+    def lists(self):
+        i = self.info
+        near_ptr = np.zeros(self.b + 1, np.int32)
+        near_idx = np.zeros(i["near_nnz"], np.int32)
+        colour = np.zeros(self.b, np.int32)
+        boff = np.zeros(i["near_nnz"], np.int64)
+        check(lib().blr_plan_lists(self._h, near_ptr.ctypes.data_as(_lib.P_i32),
+                                   near_idx.ctypes.data_as(_lib.P_i32),
+                                   colour.ctypes.data_as(_lib.P_i32),
+                                   boff.ctypes.data_as(_lib.P_i64)))
+        return near_ptr, near_idx, colour, boff
+
+    def tags(self):
+        z = np.zeros((self.b, self.ell), order="F")
+        rho = np.zeros(self.b)
+        check(lib().blr_plan_tags(self._h, z.ctypes.data_as(_lib.P_f64), rho.ctypes.data_as(_lib.P_f64)))
+        return z, rho
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().blr_plan_destroy(h)
+            self._h = None
+
+
+class Operator:
+    """A black-box operator held by the library (dense or kernel matrix)."""
+
+    def __init__(self, handle, n, keep=None):
+        self._h = handle
+        self.n = n
+        self._keep = keep
+
+    @classmethod
+    def dense(cls, A):
+        """A: column-major CUDA float64 tensor n x n (borrowed; kept alive here)."""
+        h = c_void_p()
+        check(lib().blr_op_dense_create(A.shape[0], _ptr(A), _ld(A), byref(h)))
+        return cls(h, A.shape[0], keep=A)
+
+    @classmethod
+    def kernel(cls, kind: str, pts):
+        p = np.ascontiguousarray(pts, dtype=np.float64)
+        h = c_void_p()
+        check(lib().blr_op_kernel_create(KERNELS[kind], p.shape[1], p.shape[0],
+                                         p.ctypes.data_as(_lib.P_f64), byref(h)))
+        return cls(h, p.shape[0])
+
+    def apply(self, X, trans: bool = False, stream=None):
+        Y = colmajor_empty(self.n, X.shape[1], X.device)
+        check(lib().blr_op_apply(self._h, 1 if trans else 0, X.shape[1], _ptr(X), _ld(X), _ptr(Y),
+                                 _ld(Y), _stream(stream)))
+        return Y
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().blr_op_destroy(h)
+            self._h = None
+
+
+class UBLR:
+    """Compressed A ~ U Atil V* + B owned by the library."""
+
+    def __init__(self, handle, plan: Plan):
+        self._h = handle
+        self.plan = plan
+
+    def part_ptr(self, name: str):
+        ptr = c_void_p()
+        cnt = c_int64()
+        check(lib().blr_ublr_part_ptr(self._h, PARTS[name], byref(ptr), byref(cnt)))
+        return ptr.value, cnt.value
+
+    def part(self, name: str):
+        """A copy of one part as a torch CUDA tensor (matrices column-major)."""
+        torch = _torch()
+        ptr, cnt = self.part_ptr(name)
+        n, k, r, ell, b = self.plan.n, self.plan.k, self.plan.r, self.plan.ell, self.plan.b
+        shapes = {"U": (n, k), "V": (n, k), "Atil": (b * k, b * k), "B": (cnt, 1),
+                  "Y": (n, ell * r), "Z": (n, ell * r), "Yhat": (n, r), "Zhat": (n, r)}
+        rows, cols = shapes[name]
+        view = torch.as_tensor(_DeviceView(ptr, rows, cols), device="cuda")
+        return view.clone(memory_format=torch.preserve_format) if cols == 1 else \
+            colmajor_copy(view)
+
+    def apply(self, x, trans: bool = False, stream=None):
+        y = colmajor_empty(self.plan.n, x.shape[1], x.device)
+        check(lib().blr_apply(self._h, 1 if trans else 0, x.shape[1], _ptr(x), _ld(x), _ptr(y),
+                              _ld(y), _stream(stream)))
+        return y
+
+    def error_fro(self, op: Operator, stream=None) -> float:
+        e = c_double()
+        check(lib().blr_error_fro(self._h, op._h, _stream(stream), byref(e)))
+        return e.value
+
+    def error_power(self, op: Operator, x0, iters: int = 20, stream=None):
+        e, a = c_double(), c_double()
+        check(lib().blr_error_power(self._h, op._h, _ptr(x0), iters, _stream(stream), byref(e), byref(a)))
+        return e.value, a.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().blr_ublr_destroy(h)
+            self._h = None
+
+
+def compress(plan: Plan, op: Operator, G, H, keep_intermediates: bool = False, report: bool = True,
+             stream=None):
+    """reconstruct_tag (Table 1).  Returns (UBLR, report dict or None)."""
+    opts = _lib.CompressOpts(0, 1 if keep_intermediates else 0)
+    h = c_void_p()
+    rep = _lib.Report()
+    check(lib().blr_tag_compress(plan._h, op._h, _ptr(G), _ptr(H), byref(opts), _stream(stream),
+                                 byref(h), byref(rep) if report else None))
+    out = UBLR(h, plan)
+    rd = {f: getattr(rep, f) for f, _ in _lib.Report._fields_} if report else None
+    return out, rd
+
+
+# ---------------------------------------------------------------- stages
+def sketch(plan: Plan, op: Operator, G, H, stream=None):
+    LR = plan.ell * plan.r
+    Y = colmajor_empty(plan.n, LR, G.device)
+    Z = colmajor_empty(plan.n, LR, G.device)
+    check(lib().blr_sketch(plan._h, op._h, _ptr(G), _ptr(H), _ptr(Y), _ptr(Z), _stream(stream)))
+    return Y, Z
+
+
+def postprocess(plan: Plan, Y, Z, stream=None):
+    Yh = colmajor_empty(plan.n, plan.r, Y.device)
+    Zh = colmajor_empty(plan.n, plan.r, Z.device)
+    check(lib().blr_tag_postprocess(plan._h, _ptr(Y), _ptr(Z), _ptr(Yh), _ptr(Zh), _stream(stream)))
+    return Yh, Zh
+
+
+def orthonormalize(plan: Plan, S, stream=None):
+    """Q (N x k) and sigma (b x r) from the per-box samples in S (S is consumed)."""
+    torch = _torch()
+    Q = colmajor_empty(plan.n, plan.k, S.device)
+    sig = torch.empty((plan.b, plan.r), dtype=torch.float64, device=S.device)
+    check(lib().blr_orthonormalize(plan._h, _ptr(S), _ptr(Q), _ptr(sig), _stream(stream)))
+    return Q, sig
+
+
+def cores(plan: Plan, op: Operator, U, V, stream=None):
+    bk = plan.b * plan.k
+    At = colmajor_empty(bk, bk, U.device)
+    check(lib().blr_cores(plan._h, op._h, _ptr(U), _ptr(V), _ptr(At), _stream(stream)))
+    return At
+
+
+def nearfield(plan: Plan, op: Operator, U, V, Atil, stream=None):
+    torch = _torch()
+    Bv = torch.empty(plan.info["b_values"], dtype=torch.float64, device=U.device)
+    check(lib().blr_nearfield(plan._h, op._h, _ptr(U), _ptr(V), _ptr(Atil), _ptr(Bv), _stream(stream)))
+    return Bv

@@ -1,0 +1,618 @@
+// C ABI of the tagged uBLR library (declared in include/blr_tag.h): argument
+// validation, ownership, device tables, stage sequencing and reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace blr {
+
+namespace {
+thread_local std::string g_last_error;
+
+#define HIPC(x)                                                                          \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) fail(BLR_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+T* upload(const std::vector<T>& v) {
+    T* p = nullptr;
+    const size_t n = std::max<size_t>(1, v.size());
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) fail(BLR_ERR_OOM, "device allocation of plan tables");
+    if (!v.empty()) HIPC(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+double* dalloc(int64_t count, hipStream_t s) {
+    void* p = nullptr;
+    const size_t bytes = static_cast<size_t>(std::max<int64_t>(1, count)) * sizeof(double);
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        std::ostringstream os;
+        os << "device allocation of " << bytes << " bytes failed";
+        fail(BLR_ERR_OOM, os.str());
+    }
+    return static_cast<double*>(p);
+}
+
+double* dalloc_sync(int64_t count) {
+    void* p = nullptr;
+    const size_t bytes = static_cast<size_t>(std::max<int64_t>(1, count)) * sizeof(double);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        std::ostringstream os;
+        os << "device allocation of " << bytes << " bytes failed";
+        fail(BLR_ERR_OOM, os.str());
+    }
+    return static_cast<double*>(p);
+}
+
+// Frees stream-ordered temporaries when a call leaves (normally or by error).
+struct AsyncTemps {
+    hipStream_t s;
+    std::vector<double*> ptrs;
+    explicit AsyncTemps(hipStream_t st) : s(st) {}
+    double* get(int64_t count) {
+        ptrs.push_back(dalloc(count, s));
+        return ptrs.back();
+    }
+    ~AsyncTemps() {
+        for (double* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+};
+
+int current_device() {
+    int d = -1;
+    HIPC(hipGetDevice(&d));
+    return d;
+}
+
+const blr::PlanData& plan_of(const blr_plan* p) {
+    if (!p || !p->d) fail(BLR_ERR_INVALID_ARG, "NULL plan");
+    return *p->d;
+}
+
+const blr::OpData& op_of(const blr_operator* o, const PlanData& P) {
+    if (!o || !o->d) fail(BLR_ERR_INVALID_ARG, "NULL operator");
+    if (o->d->n != P.n) fail(BLR_ERR_INVALID_ARG, "operator size differs from the plan's N");
+    if (o->d->device != current_device()) fail(BLR_ERR_INVALID_ARG, "operator belongs to another device");
+    return *o->d;
+}
+
+template <class F>
+blr_status guard(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return BLR_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return BLR_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return BLR_ERR_INVALID_ARG;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return BLR_ERR_INVALID_ARG;
+    }
+}
+
+void check_ld(int64_t ld, int64_t n, const char* what) {
+    if (ld < n) fail(BLR_ERR_INVALID_ARG, std::string(what) + " leading dimension is smaller than N");
+}
+
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void DeviceTables::release() {
+    dfree(box_ptr);
+    dfree(row_box);
+    dfree(T);
+    dfree(z);
+    dfree(near_ptr);
+    dfree(near_idx);
+    dfree(near_tpos);
+    dfree(b_off);
+    dfree(colour_ptr);
+    dfree(colour_boxes);
+    dfree(nf_pair);
+}
+
+const DeviceTables& PlanData::tables() {
+    const int devid = current_device();
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& t : dev)
+        if (t->device == devid) return *t;
+    auto t = std::make_unique<DeviceTables>();
+    t->device = devid;
+    try {
+        std::vector<double> Trm(static_cast<size_t>(b) * ell), zrm(static_cast<size_t>(b) * ell);
+        for (int i = 0; i < b; ++i)
+            for (int s = 0; s < ell; ++s) {
+                Trm[static_cast<size_t>(i) * ell + s] = T[i + static_cast<size_t>(s) * b];
+                zrm[static_cast<size_t>(i) * ell + s] = z[i + static_cast<size_t>(s) * b];
+            }
+        t->box_ptr = upload(box_ptr);
+        t->row_box = upload(row_box);
+        t->T = upload(Trm);
+        t->z = upload(zrm);
+        t->near_ptr = upload(near_ptr);
+        t->near_idx = upload(near_idx);
+        t->near_tpos = upload(near_tpos);
+        t->b_off = upload(b_off);
+        t->colour_ptr = upload(colour_ptr);
+        t->colour_boxes = upload(colour_boxes);
+        t->nf_pair = upload(nf_pair);
+    } catch (...) {
+        t->release();
+        throw;
+    }
+    dev.push_back(std::move(t));
+    return *dev.back();
+}
+
+PlanData::~PlanData() {
+    if (dev.empty()) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (auto& t : dev) {
+        (void)hipSetDevice(t->device);
+        t->release();
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+}
+
+OpData::~OpData() { dfree(pts); }
+
+UblrData::~UblrData() {
+    dfree(U);
+    dfree(V);
+    dfree(Atil);
+    dfree(B);
+    dfree(Y);
+    dfree(Z);
+    dfree(Yhat);
+    dfree(Zhat);
+}
+
+}  // namespace blr
+
+using namespace blr;
+
+extern "C" {
+
+const char* blr_status_string(blr_status s) {
+    switch (s) {
+        case BLR_OK: return "BLR_OK";
+        case BLR_ERR_INVALID_ARG: return "BLR_ERR_INVALID_ARG";
+        case BLR_ERR_GEOMETRY: return "BLR_ERR_GEOMETRY";
+        case BLR_ERR_OOM: return "BLR_ERR_OOM";
+        case BLR_ERR_DEVICE: return "BLR_ERR_DEVICE";
+        case BLR_ERR_OPERATOR: return "BLR_ERR_OPERATOR";
+        case BLR_ERR_NUMERICAL: return "BLR_ERR_NUMERICAL";
+        case BLR_ERR_BUSY: return "BLR_ERR_BUSY";
+        case BLR_ERR_UNSUPPORTED: return "BLR_ERR_UNSUPPORTED";
+    }
+    return "BLR_ERR_UNKNOWN";
+}
+
+const char* blr_last_error_message(void) { return g_last_error.c_str(); }
+
+const char* blr_version(void) { return "blrtag-mi355x 0.1 (gfx950)"; }
+
+blr_status blr_tag_columns(const blr_geometry* geom, int32_t extra_tag_cols, int32_t* ell_out) {
+    if (ell_out) *ell_out = 0;
+    return guard([&] {
+        if (!ell_out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        *ell_out = tag_columns(geom, extra_tag_cols);
+    });
+}
+
+blr_status blr_tag_plan(const blr_geometry* geom, const blr_tag_params* params, blr_plan** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        auto d = build_plan(geom, params);
+        // T must have exactly ell columns; the caller sized it with blr_tag_columns.
+        auto* p = new blr_plan;
+        p->d = std::move(d);
+        *out = p;
+    });
+}
+
+void blr_plan_destroy(blr_plan* plan) { delete plan; }
+
+blr_status blr_plan_query(const blr_plan* plan, blr_plan_info* info) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (!info) fail(BLR_ERR_INVALID_ARG, "NULL info");
+        info->n = P.n;
+        info->nboxes = P.b;
+        info->dim = P.dim;
+        info->k = P.k;
+        info->p = P.p;
+        info->r = P.r;
+        info->ell = P.ell;
+        info->m_max = P.m_max;
+        info->m_min = P.m_min;
+        info->ncolours = P.ncol;
+        info->near_nnz = P.near_nnz;
+        info->b_values = P.b_values;
+    });
+}
+
+blr_status blr_plan_lists(const blr_plan* plan, int32_t* near_ptr, int32_t* near_idx,
+                          int32_t* colour, int64_t* b_offset) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (near_ptr) std::copy(P.near_ptr.begin(), P.near_ptr.end(), near_ptr);
+        if (near_idx) std::copy(P.near_idx.begin(), P.near_idx.end(), near_idx);
+        if (colour) std::copy(P.colour.begin(), P.colour.end(), colour);
+        if (b_offset) std::copy(P.b_off.begin(), P.b_off.end(), b_offset);
+    });
+}
+
+blr_status blr_plan_tags(const blr_plan* plan, double* z, double* rho) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (z) std::copy(P.z.begin(), P.z.end(), z);
+        if (rho) std::copy(P.rho.begin(), P.rho.end(), rho);
+    });
+}
+
+blr_status blr_op_dense_create(int64_t n, const double* A, int64_t lda, blr_operator** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out || !A) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (n <= 0 || lda < n) fail(BLR_ERR_INVALID_ARG, "need n > 0 and lda >= n");
+        auto d = std::make_unique<OpData>();
+        d->type = OpType::Dense;
+        d->n = n;
+        d->A = A;
+        d->lda = lda;
+        d->device = current_device();
+        auto* o = new blr_operator;
+        o->d = std::move(d);
+        *out = o;
+    });
+}
+
+blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const double* pts,
+                                blr_operator** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out || !pts) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (kind < BLR_KERNEL_LOG || kind > BLR_KERNEL_COS) fail(BLR_ERR_INVALID_ARG, "unknown kernel kind");
+        if (dim < 1 || dim > 3 || n <= 0) fail(BLR_ERR_INVALID_ARG, "need 1 <= dim <= 3 and n > 0");
+        std::vector<double> soa(static_cast<size_t>(3) * n, 0.0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int t = 0; t < dim; ++t) {
+                const double v = pts[i * dim + t];
+                if (!std::isfinite(v)) fail(BLR_ERR_INVALID_ARG, "non-finite point coordinate");
+                soa[static_cast<size_t>(t) * n + i] = v;
+            }
+        auto d = std::make_unique<OpData>();
+        d->type = OpType::Kernel;
+        d->n = n;
+        d->kind = kind;
+        d->dim = dim;
+        d->device = current_device();
+        d->pts = dalloc_sync(3 * n);
+        HIPC(hipMemcpy(d->pts, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+        auto* o = new blr_operator;
+        o->d = std::move(d);
+        *out = o;
+    });
+}
+
+void blr_op_destroy(blr_operator* op) { delete op; }
+
+blr_status blr_op_apply(const blr_operator* op, int32_t trans, int64_t ncols, const double* X,
+                        int64_t ldx, double* Y, int64_t ldy, void* stream) {
+    return guard([&] {
+        if (!op || !op->d) fail(BLR_ERR_INVALID_ARG, "NULL operator");
+        const OpData& o = *op->d;
+        if (ncols < 0) fail(BLR_ERR_INVALID_ARG, "negative ncols");
+        if (ncols == 0) return;
+        if (!X || !Y) fail(BLR_ERR_INVALID_ARG, "NULL X or Y");
+        check_ld(ldx, o.n, "X");
+        check_ld(ldy, o.n, "Y");
+        if (o.device != current_device()) fail(BLR_ERR_INVALID_ARG, "operator belongs to another device");
+        launch_op_apply(o, trans ? 1 : 0, ncols, X, ldx, Y, ldy, static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_sketch(const blr_plan* plan, const blr_operator* op, const double* G,
+                      const double* H, double* Y, double* Z, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!G || !H || !Y || !Z) fail(BLR_ERR_INVALID_ARG, "NULL G, H, Y or Z");
+        const DeviceTables& t = plan->d->tables();
+        launch_sketch(o, P, t, G, H, Y, Z, static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_tag_postprocess(const blr_plan* plan, const double* Y, const double* Z,
+                               double* Yhat, double* Zhat, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if ((Y == nullptr) != (Yhat == nullptr) || (Z == nullptr) != (Zhat == nullptr))
+            fail(BLR_ERR_INVALID_ARG, "input and output of a side must both be given");
+        const DeviceTables& t = plan->d->tables();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (Y) launch_postprocess(P, t, Y, Yhat, s);
+        if (Z) launch_postprocess(P, t, Z, Zhat, s);
+    });
+}
+
+blr_status blr_orthonormalize(const blr_plan* plan, double* S, double* Q, double* sigma,
+                              void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (!S || !Q) fail(BLR_ERR_INVALID_ARG, "NULL S or Q");
+        const DeviceTables& t = plan->d->tables();
+        launch_orth(P, t, S, Q, sigma, static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_cores(const blr_plan* plan, const blr_operator* op, const double* U,
+                     const double* V, double* Atil, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!U || !V || !Atil) fail(BLR_ERR_INVALID_ARG, "NULL U, V or Atil");
+        const DeviceTables& t = plan->d->tables();
+        launch_cores(o, P, t, U, V, Atil, static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const double* U,
+                         const double* V, const double* Atil, double* Bvals, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!U || !V || !Atil || !Bvals) fail(BLR_ERR_INVALID_ARG, "NULL U, V, Atil or B");
+        const DeviceTables& t = plan->d->tables();
+        launch_nearfield(o, P, t, U, V, Atil, Bvals, static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
+                            const double* H, const blr_compress_opts* opts, void* stream,
+                            blr_ublr** out, blr_report* rep) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!G || !H) fail(BLR_ERR_INVALID_ARG, "NULL G or H");
+        blr_compress_opts def{BLR_PREC_FP64, 0};
+        const blr_compress_opts& O = opts ? *opts : def;
+        if (O.precision != BLR_PREC_FP64) fail(BLR_ERR_UNSUPPORTED, "unsupported precision");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = plan->d->tables();
+        const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+        const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+
+        auto h = std::make_unique<UblrData>();
+        h->plan = plan->d;
+        h->device = current_device();
+        h->U = dalloc_sync(P.n * P.k);
+        h->V = dalloc_sync(P.n * P.k);
+        h->Atil = dalloc_sync(bk * bk);
+        h->B = dalloc_sync(P.b_values);
+        AsyncTemps tmp(s);
+        double *Y, *Z, *Yh, *Zh;
+        if (O.keep_intermediates) {
+            h->Y = Y = dalloc_sync(P.n * LR);
+            h->Z = Z = dalloc_sync(P.n * LR);
+            h->Yhat = dalloc_sync(P.n * P.r);
+            h->Zhat = dalloc_sync(P.n * P.r);
+        } else {
+            Y = tmp.get(P.n * LR);
+            Z = tmp.get(P.n * LR);
+        }
+        Yh = tmp.get(P.n * P.r);
+        Zh = tmp.get(P.n * P.r);
+
+        hipEvent_t ev[6];
+        const bool timing = rep != nullptr;
+        if (timing)
+            for (auto& e : ev) HIPC(hipEventCreate(&e));
+        auto mark = [&](int q) {
+            if (timing) HIPC(hipEventRecord(ev[q], s));
+        };
+        mark(0);
+        launch_sketch(o, P, t, G, H, Y, Z, s);
+        mark(1);
+        launch_postprocess(P, t, Y, Yh, s);
+        launch_postprocess(P, t, Z, Zh, s);
+        if (O.keep_intermediates) {
+            HIPC(hipMemcpyAsync(h->Yhat, Yh, P.n * P.r * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(h->Zhat, Zh, P.n * P.r * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        mark(2);
+        launch_orth(P, t, Yh, h->U, nullptr, s);
+        launch_orth(P, t, Zh, h->V, nullptr, s);
+        mark(3);
+        launch_cores(o, P, t, h->U, h->V, h->Atil, s);
+        mark(4);
+        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, s);
+        mark(5);
+        if (timing) {
+            HIPC(hipStreamSynchronize(s));
+            float ms[5];
+            for (int q = 0; q < 5; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+            float tot;
+            HIPC(hipEventElapsedTime(&tot, ev[0], ev[5]));
+            for (auto& e : ev) (void)hipEventDestroy(e);
+            std::memset(rep, 0, sizeof(*rep));
+            rep->ms_sketch = ms[0];
+            rep->ms_postprocess = ms[1];
+            rep->ms_orth = ms[2];
+            rep->ms_cores = ms[3];
+            rep->ms_nearfield = ms[4];
+            rep->ms_total = tot;
+            rep->applies_A = LR + bk + static_cast<int64_t>(P.ncol) * P.m_max;
+            rep->applies_At = LR;
+            rep->sketch_flops = 4.0 * static_cast<double>(P.n) * static_cast<double>(P.n) * static_cast<double>(LR);
+            std::vector<double> rho = P.rho;
+            std::sort(rho.begin(), rho.end());
+            rep->rho_min = rho.front();
+            rep->rho_max = rho.back();
+            rep->rho_median = rho[rho.size() / 2];
+        }
+        auto* hh = new blr_ublr;
+        hh->d = std::move(h);
+        *out = hh;
+    });
+}
+
+void blr_ublr_destroy(blr_ublr* h) { delete h; }
+
+blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const double** ptr, int64_t* count) {
+    if (ptr) *ptr = nullptr;
+    return guard([&] {
+        if (!h || !h->d || !ptr || !count) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+        const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+        switch (part) {
+            case BLR_PART_U: *ptr = d.U; *count = P.n * P.k; break;
+            case BLR_PART_V: *ptr = d.V; *count = P.n * P.k; break;
+            case BLR_PART_ATIL: *ptr = d.Atil; *count = bk * bk; break;
+            case BLR_PART_B: *ptr = d.B; *count = P.b_values; break;
+            case BLR_PART_Y: *ptr = d.Y; *count = P.n * LR; break;
+            case BLR_PART_Z: *ptr = d.Z; *count = P.n * LR; break;
+            case BLR_PART_YHAT: *ptr = d.Yhat; *count = P.n * P.r; break;
+            case BLR_PART_ZHAT: *ptr = d.Zhat; *count = P.n * P.r; break;
+            default: fail(BLR_ERR_INVALID_ARG, "unknown part");
+        }
+        if (!*ptr) fail(BLR_ERR_INVALID_ARG, "part not kept (compress with keep_intermediates)");
+    });
+}
+
+blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x, int64_t ldx,
+                     double* y, int64_t ldy, void* stream) {
+    return guard([&] {
+        if (!h || !h->d) fail(BLR_ERR_INVALID_ARG, "NULL handle");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        if (ncols < 0) fail(BLR_ERR_INVALID_ARG, "negative ncols");
+        if (ncols == 0) return;
+        if (ncols > 65535) fail(BLR_ERR_INVALID_ARG, "at most 65535 columns per call");
+        if (!x || !y) fail(BLR_ERR_INVALID_ARG, "NULL x or y");
+        check_ld(ldx, P.n, "x");
+        check_ld(ldy, P.n, "y");
+        if (d.device != current_device()) fail(BLR_ERR_INVALID_ARG, "handle belongs to another device");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = d.plan->tables();
+        AsyncTemps tmp(s);
+        double* work = tmp.get(apply_workspace_doubles(P, ncols));
+        launch_ublr_apply(P, t, d.U, d.V, d.Atil, d.B, trans ? 1 : 0, ncols, x, ldx, y, ldy, work, s);
+    });
+}
+
+blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream, double* rel_err) {
+    return guard([&] {
+        if (!h || !h->d || !rel_err) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        const OpData& o = op_of(op, P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = d.plan->tables();
+        AsyncTemps tmp(s);
+        const int64_t np = static_cast<int64_t>(P.b) * P.b;
+        double* part = tmp.get(2 * np);
+        launch_err_fro(o, P, t, d.U, d.V, d.Atil, d.B, part, s);
+        std::vector<double> hp(2 * np);
+        HIPC(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        double se = 0.0, sa = 0.0;
+        for (int64_t q = 0; q < np; ++q) {
+            se += hp[2 * q];
+            sa += hp[2 * q + 1];
+        }
+        *rel_err = sa > 0.0 ? std::sqrt(se / sa) : std::sqrt(se);
+    });
+}
+
+blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const double* x0,
+                           int32_t iters, void* stream, double* err_norm, double* a_norm) {
+    return guard([&] {
+        if (!h || !h->d || !x0) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (iters < 1) fail(BLR_ERR_INVALID_ARG, "iters must be >= 1");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        const OpData& o = op_of(op, P);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = d.plan->tables();
+        const int64_t n = P.n;
+        AsyncTemps tmp(s);
+        double* x = tmp.get(n);
+        double* y = tmp.get(n);
+        double* w = tmp.get(n);
+        double* u = tmp.get(n);
+        double* part = tmp.get(dot_parts());
+        double* work = tmp.get(apply_workspace_doubles(P, 1));
+        auto norm2 = [&](const double* v) {
+            launch_dot(v, v, n, part, s);
+            double r = 0.0;
+            HIPC(hipMemcpyAsync(&r, part, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            return std::sqrt(r);
+        };
+        // M v = A v - (use_ublr ? A_uBLR v : 0); M* likewise
+        auto apply_M = [&](int trans, bool diff, const double* in, double* out) {
+            launch_op_apply(o, trans, 1, in, n, out, n, s);
+            if (diff) {
+                launch_ublr_apply(P, t, d.U, d.V, d.Atil, d.B, trans, 1, in, n, u, n, work, s);
+                launch_axpy(-1.0, u, out, n, s);
+            }
+        };
+        auto power = [&](bool diff) {
+            HIPC(hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            const double n0 = norm2(x);
+            if (n0 == 0.0) fail(BLR_ERR_INVALID_ARG, "x0 is zero");
+            launch_scale(1.0 / n0, x, n, s);
+            for (int it = 0; it < iters; ++it) {
+                apply_M(0, diff, x, y);
+                apply_M(1, diff, y, w);
+                const double nw = norm2(w);
+                if (nw == 0.0 || !std::isfinite(nw)) {
+                    if (!std::isfinite(nw)) fail(BLR_ERR_NUMERICAL, "non-finite power iterate");
+                    return 0.0;
+                }
+                launch_scale(1.0 / nw, w, n, s);
+                std::swap(x, w);
+            }
+            apply_M(0, diff, x, y);
+            return norm2(y);
+        };
+        const double e = power(true);
+        if (err_norm) *err_norm = e;
+        if (a_norm) *a_norm = power(false);
+    });
+}
+
+}  // extern "C"

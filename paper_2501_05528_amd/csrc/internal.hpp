@@ -1,0 +1,98 @@
+// Internal types shared by the host planner, the C ABI glue and the HIP
+// kernels of the tagged uBLR library.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/blr_tag.h"
+
+namespace blr {
+
+// Internal failures are thrown as Error and converted to a status code at
+// the ABI boundary (no exception crosses it).
+struct Error : std::runtime_error {
+    blr_status status;
+    Error(blr_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+[[noreturn]] inline void fail(blr_status s, const std::string& m) { throw Error(s, m); }
+
+void set_last_error(const std::string& msg);
+
+// Device copies of a plan's tables (one set per device that used the plan).
+struct DeviceTables {
+    int device = -1;
+    int64_t* box_ptr = nullptr;      // [b+1]
+    int32_t* row_box = nullptr;      // [N] box of each row
+    double* T = nullptr;             // [b*ell] row-major (T(i, s) at i*ell + s)
+    double* z = nullptr;             // [b*ell] row-major tag vectors
+    int32_t* near_ptr = nullptr;     // [b+1]
+    int32_t* near_idx = nullptr;     // [nnz]
+    int32_t* near_tpos = nullptr;    // [nnz] index of pair (j, i) for pair (i, j)
+    int64_t* b_off = nullptr;        // [nnz] offsets of B blocks
+    int32_t* colour_ptr = nullptr;   // [ncol+1] CSR of boxes per colour
+    int32_t* colour_boxes = nullptr; // [b]
+    int32_t* nf_pair = nullptr;      // [b*ncol] near pair index of (i, colour) or -1
+    void release();
+};
+
+struct PlanData {
+    int dim = 0, b = 0, k = 0, p = 0, r = 0, ell = 0, extra = 0, ncol = 0;
+    int m_max = 0, m_min = 0;
+    int aspect_opt = 1;
+    int64_t n = 0, near_nnz = 0, b_values = 0;
+    std::vector<int64_t> box_ptr;
+    std::vector<int32_t> lattice;
+    std::vector<int32_t> near_ptr, near_idx, near_tpos, colour, colour_ptr, colour_boxes, nf_pair, row_box;
+    std::vector<int64_t> b_off;
+    std::vector<double> T;    // column-major b x ell (as supplied)
+    std::vector<double> z;    // column-major b x ell
+    std::vector<double> rho;  // [b]
+
+    std::mutex mu;
+    std::vector<std::unique_ptr<DeviceTables>> dev;
+    const DeviceTables& tables();  // tables for the current device (uploads on first use)
+    ~PlanData();
+};
+
+// Host planner (plan.cpp).
+std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params* prm);
+int tag_columns(const blr_geometry* g, int extra);
+
+// Operators.
+enum class OpType { Dense, Kernel };
+struct OpData {
+    OpType type = OpType::Dense;
+    int64_t n = 0;
+    int kind = 0;                 // blr_kernel_kind
+    int dim = 0;
+    const double* A = nullptr;    // dense, borrowed
+    int64_t lda = 0;
+    double* pts = nullptr;        // kernel: device SoA [3][n] (unused axes zero), owned
+    int device = -1;
+    ~OpData();
+};
+
+struct UblrData {
+    std::shared_ptr<PlanData> plan;
+    int device = -1;
+    double* U = nullptr;
+    double* V = nullptr;
+    double* Atil = nullptr;
+    double* B = nullptr;
+    double* Y = nullptr;
+    double* Z = nullptr;
+    double* Yhat = nullptr;
+    double* Zhat = nullptr;
+    ~UblrData();
+};
+
+}  // namespace blr
+
+struct blr_plan { std::shared_ptr<blr::PlanData> d; };
+struct blr_operator { std::unique_ptr<blr::OpData> d; };
+struct blr_ublr { std::unique_ptr<blr::UblrData> d; };

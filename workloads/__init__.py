@@ -220,3 +220,37 @@ def uneven_batch_jobs(njobs: int, seed: int, n_lo: int = 4096, n_hi: int = 13107
         jobs.append(Workload(f"job{t}", 2, (B, B), (qx, qy), k, kind, seed * 1000 + t,
                              jitter=0.25))
     return jobs
+
+
+def irregular_grid_geometry(widths_per_axis, jitter: float = 0.0, seed: int = 0) -> Geometry:
+    """Cell-centred grid whose boxes have uneven sizes.
+
+    ``widths_per_axis[t]`` lists the number of grid points of each box along
+    axis t (so box sizes differ); the grid has sum(widths) points on that axis.
+    Boxes are numbered x fastest and points inside a box are ordered x fastest.
+    """
+    dim = len(widths_per_axis)
+    W = [list(map(int, w)) for w in widths_per_axis]
+    B = [len(w) for w in W]
+    n_axis = [sum(w) for w in W]
+    starts = [np.concatenate([[0], np.cumsum(w)[:-1]]) for w in W]
+    nb = int(np.prod(B))
+    lattice = np.zeros((nb, dim), dtype=np.int32)
+    pts_list, sizes = [], []
+    for i in range(nb):
+        rem = i
+        for t in range(dim):
+            lattice[i, t] = rem % B[t]
+            rem //= B[t]
+        axes = [np.arange(starts[t][lattice[i, t]], starts[t][lattice[i, t]] + W[t][lattice[i, t]])
+                for t in range(dim)]
+        mesh = np.meshgrid(*axes, indexing="ij")          # axis 0 = x
+        g = np.stack([m.reshape(-1, order="F") for m in mesh], axis=1)
+        pts_list.append((g + 0.5) / np.array(n_axis, dtype=float))
+        sizes.append(g.shape[0])
+    pts = np.concatenate(pts_list, axis=0)
+    if jitter:
+        h = 1.0 / np.array(n_axis, dtype=float)
+        pts = pts + jitter * rng(seed, STREAM_JITTER).uniform(-1.0, 1.0, size=pts.shape) * h[None, :]
+    box_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return Geometry(dim, np.ascontiguousarray(pts), box_ptr, lattice, tuple(B), tuple(0 for _ in B))
