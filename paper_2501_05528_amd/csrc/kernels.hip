@@ -48,10 +48,45 @@ __device__ inline double wave_sum(double v) {
 
 // ------------------------------------------------------------ entry sources
 // A source yields A(i, j) from a row context and a column context.
+// Natural logarithm of a positive, finite, normal x.  x = 2^e m with m in
+// [1/sqrt(2), sqrt(2)); log m = 2 atanh(f) with f = (m - 1)/(m + 1), |f| <= 0.1716,
+// summed as 2f (1 + f^2/3 + f^4/5 + ... + f^20/21) (the first omitted term is
+// below 1e-18 relative); ln 2 is split into a head with 21 trailing zero bits
+// (e * head is exact) and a tail.  The quotient f gets two Newton steps on the
+// hardware reciprocal and one residual correction.  About 1 ulp.
+__device__ inline double log_pos(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool lo = m < 0.7071067811865476;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double num = m - 1.0, den = m + 1.0;
+    double q = __builtin_amdgcn_rcp(den);
+    q = fma(fma(-den, q, 1.0), q, q);
+    q = fma(fma(-den, q, 1.0), q, q);
+    double f = num * q;
+    f = fma(fma(-den, f, num), q, f);
+    const double s2 = f * f;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double t = 2.0 * f;
+    const double lm = fma(t * s2, p, t);
+    const double de = static_cast<double>(e);
+    return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, lm));
+}
+
 template <int KIND>
 __device__ inline double kval(double r2) {
     if constexpr (KIND == BLR_KERNEL_LOG) {
-        return 0.5 * log(r2);
+        return 0.5 * log_pos(r2);
     } else if constexpr (KIND == BLR_KERNEL_INV_R) {
         return 1.0 / sqrt(r2);
     } else if constexpr (KIND == BLR_KERNEL_EXP) {
@@ -155,28 +190,58 @@ struct SplitOut {  // column q < LR -> C0(:, q), else C1(:, q - LR)
 
 // ------------------------------------------------------------ operator GEMM
 // C(M x ncols) = A(M x K) * B(K x ncols), A generated by the source.  One
-// workgroup (4 waves) computes a 64 x BN tile; wave w owns columns
-// [w*BN/4, (w+1)*BN/4).  K is consumed 16 at a time through LDS.
-template <class AS, class BS, class OUT, int BN>
+// workgroup (4 waves) computes a 64 x (4*WN) tile; wave w owns columns
+// [w*WN, (w+1)*WN).  K is consumed KT = 8 at a time through double-buffered
+// LDS with one barrier per step: while the MFMAs of step k read buffer k%2,
+// the workgroup generates the A and B tiles of step k+1 into the other
+// buffer, so entry generation overlaps the matrix cores.  Generation is
+// branch-free (clamped indices, zero-select outside the matrix) and the
+// source index of an A-tile column is wave-uniform (scalar loads).
+template <class AS, class BS, class OUT, int WN>
 __global__ __launch_bounds__(256, 2) void k_opgemm(AS A, BS B, OUT O, int64_t M, int64_t K,
                                                     int ncols) {
-    constexpr int BM = 64, KT = 16, WN = BN / 4, NT = WN / 16;
+    constexpr int BM = 64, KT = 8, BN = 4 * WN, NT = WN / 16;
     constexpr int BPT = KT * BN / 256;  // B tile entries per thread
-    __shared__ double sA[KT * BM];
-    __shared__ double sB[KT * BN];
+    static_assert((KT * BN) % 256 == 0, "B tile must split evenly over 256 threads");
+    __shared__ double sA[2][KT * BM];
+    __shared__ double sB[2][KT * BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
     const int col0 = blockIdx.y * BN;
 
-    const int am = tid & 63, ak = (tid >> 6) * 4;
+    // A generation: thread (am = lane, kk = 2*wave + u), u < 2
+    const int am = lane;
     const int64_t gi = row0 + am;
     const bool rowok = gi < M;
-    const auto rp = A.row(rowok ? gi : 0);
+    const auto rp = A.row(rowok ? gi : M - 1);
+    // B generation: element e = tid + 256*u of the KT x BN tile (fixed per thread)
+    typename BS::C cpu[BPT];
+    bool cok[BPT];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int e = tid + 256 * u;
+        const int q = col0 + e % BN;
+        cok[u] = q < ncols;
+        cpu[u] = B.col(q < ncols ? q : ncols - 1);
+    }
 
-    const int bn = tid % BN, bk0 = (tid / BN) * BPT;
-    const int q = col0 + bn;
-    const bool colok = q < ncols;
-    const auto cp = B.col(colok ? q : 0);
+    auto gen = [&](int buf, int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int kk = 2 * wave + u;
+            int64_t j = __builtin_amdgcn_readfirstlane(static_cast<int>(min<int64_t>(k0 + kk, K - 1)));
+            double v = A.val(rp, A.col(j));
+            sA[buf][kk * BM + am] = (rowok && k0 + kk < K) ? v : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int e = tid + 256 * u;
+            const int kk = e / BN;
+            const int64_t j = min<int64_t>(k0 + kk, K - 1);
+            const double v = B.val(j, cpu[u]);
+            sB[buf][e] = (cok[u] && k0 + kk < K) ? v : 0.0;
+        }
+    };
 
     d4 acc[4][NT];
 #pragma unroll
@@ -184,38 +249,26 @@ __global__ __launch_bounds__(256, 2) void k_opgemm(AS A, BS B, OUT O, int64_t M,
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
 
+    gen(0, 0);
+    __syncthreads();
+    int buf = 0;
     for (int64_t k0 = 0; k0 < K; k0 += KT) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kk = ak + u;
-            const int64_t j = k0 + kk;
-            double v = 0.0;
-            if (rowok && j < K) v = A.val(rp, A.col(j));
-            sA[kk * BM + am] = v;
-        }
-#pragma unroll
-        for (int u = 0; u < BPT; ++u) {
-            const int kk = bk0 + u;
-            const int64_t j = k0 + kk;
-            double v = 0.0;
-            if (colok && j < K) v = B.val(j, cp);
-            sB[kk * BN + bn] = v;
-        }
-        __syncthreads();
+        if (k0 + KT < K) gen(buf ^ 1, k0 + KT);
 #pragma unroll
         for (int ks = 0; ks < KT / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
             double a[4], bb[NT];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = sA[kr * BM + mt * 16 + (lane & 15)];
+            for (int mt = 0; mt < 4; ++mt) a[mt] = sA[buf][kr * BM + mt * 16 + (lane & 15)];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) bb[nt] = sB[kr * BN + wave * WN + nt * 16 + (lane & 15)];
+            for (int nt = 0; nt < NT; ++nt) bb[nt] = sB[buf][kr * BN + wave * WN + nt * 16 + (lane & 15)];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma64(a[mt], bb[nt], acc[mt][nt]);
         }
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -230,17 +283,242 @@ __global__ __launch_bounds__(256, 2) void k_opgemm(AS A, BS B, OUT O, int64_t M,
         }
 }
 
+// Column-tile width per wave: the widest of 64/48/32/16 that minimises padding.
+inline int pick_wn(int ncols) {
+    int best = 64;
+    int64_t best_pad = -1;
+    for (int wn : {64, 48, 32, 16}) {
+        const int64_t bn = 4 * wn;
+        const int64_t pad = ((ncols + bn - 1) / bn) * bn;
+        if (best_pad < 0 || pad < best_pad) {
+            best = wn;
+            best_pad = pad;
+        }
+    }
+    return best;
+}
+
 template <class AS, class BS, class OUT>
 void gemm_launch(AS A, BS B, OUT O, int64_t M, int64_t K, int ncols, hipStream_t s) {
     if (M <= 0 || ncols <= 0) return;
-    if (ncols > 128) {
-        dim3 grid((M + 63) / 64, (ncols + 255) / 256);
-        hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 256>), grid, dim3(256), 0, s, A, B, O, M, K, ncols);
-    } else {
-        dim3 grid((M + 63) / 64, (ncols + 63) / 64);
-        hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 64>), grid, dim3(256), 0, s, A, B, O, M, K, ncols);
+    if (K <= 0 || K > INT32_MAX) fail(BLR_ERR_INVALID_ARG, "operator GEMM: bad inner dimension");
+    const int wn = pick_wn(ncols);
+    const int bn = 4 * wn;
+    dim3 grid((M + 63) / 64, (ncols + bn - 1) / bn);
+    switch (wn) {
+        case 64: hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 64>), grid, dim3(256), 0, s, A, B, O, M, K, ncols); break;
+        case 48: hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 48>), grid, dim3(256), 0, s, A, B, O, M, K, ncols); break;
+        case 32: hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 32>), grid, dim3(256), 0, s, A, B, O, M, K, ncols); break;
+        default: hipLaunchKernelGGL((k_opgemm<AS, BS, OUT, 16>), grid, dim3(256), 0, s, A, B, O, M, K, ncols); break;
     }
     check_launch("operator GEMM");
+}
+
+// ------------------------------------------------------------ tagged sketch
+// Y(:, s*r + c) = sum_l T(l, s) A(:, I_l) G(I_l, c)  (and Z from H), i.e.
+// Y = A Omega with Omega from eq. extend_test_mat.  The K loop walks the
+// source boxes l in steps of KT rows that never straddle a box, so within a
+// step the tag weight T(l, s) is one scalar per tag column s: it scales the
+// MFMA A fragments of the generated kernel tile, and the B tile is the plain
+// rows of [G | H] (r columns each, padded to 16*NTR).
+//
+// Work split: a workgroup owns BM = 4*MA target rows and a group of up to
+// 4*SPW "slots" (a slot is one (tag column s, side) pair, ordered s-major);
+// its four waves take contiguous, balanced chunks of the slots, so a wave's
+// Y and Z columns for the same s share one scaled A fragment.  One kernel
+// entry generated into LDS feeds every slot of the workgroup.  Contractions
+// use v_mfma_f64_4x4x4f64 with the A fragment replicated over the four
+// blocks, i.e. one 4 x 16 x 4 product per instruction:
+//   A lane l: A[l % 4][l / 16];  B lane l: B[l / 16][l % 16];
+//   D lane l: D[l / 16][l % 16].
+// Tiles are double-buffered in LDS with one barrier per step; the next
+// step's [G|H] rows are fetched into registers before the current step's
+// MFMAs and stored afterwards.
+__device__ inline double mfma44(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class AS, int NTR, int NSIDE, int SVW>
+__global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restrict__ T,
+                                                    const int64_t* __restrict__ box_ptr, int nbox,
+                                                    const double* __restrict__ G0,
+                                                    const double* __restrict__ G1, int64_t n,
+                                                    int r, int ell, double* __restrict__ Y0,
+                                                    double* __restrict__ Y1) {
+    constexpr int MA = 2, BM = 4 * MA, KT = 16, CW = NTR * 16;  // rows, sources/step, cols/side
+    constexpr int BW = NSIDE * CW;                               // B tile width
+    constexpr int BPT = (KT * BW + 255) / 256;
+    constexpr int AGEN = BM * KT;                                // A tile entries per step
+    static_assert(AGEN <= 256, "tile shape");
+    __shared__ double sA[2][KT * BM];
+    __shared__ double sB[2][KT * BW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
+    // this wave's tag columns: a balanced contiguous chunk of the group's
+    const int sg0 = blockIdx.y * 4 * SVW;
+    const int sgn = min(4 * SVW, ell - sg0);
+    const int s_lo = sg0 + (wave * sgn) / 4;
+    const int nsv = sg0 + ((wave + 1) * sgn) / 4 - s_lo;
+    // A generation: threads t < AGEN own entry (row t % BM, kk = t / BM)
+    const bool agen = tid < AGEN;
+    const int arow = tid % BM, akk = tid / BM;
+    const int64_t gi = row0 + arow;
+    const auto rp = A.row(gi < n ? gi : n - 1);
+    // B tile: element e = tid + 256*u -> row e / BW, column e % BW (side = col / CW)
+    const double* gptr[BPT];
+    bool gcol[BPT], gin[BPT];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int e = tid + 256 * u;
+        const int cc = e % BW;
+        const int side = cc / CW, c = cc % CW;
+        gin[u] = e < KT * BW;
+        gcol[u] = gin[u] && c < r;
+        gptr[u] = (side ? G1 : G0) + static_cast<int64_t>(gcol[u] ? c : 0) * n;
+    }
+    double gv[BPT];
+    auto fetch_b = [&](int64_t jb, int64_t jend) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int kk = (tid + 256 * u) / BW;
+            gv[u] = gptr[u][min(jb + kk, jend - 1)];
+        }
+    };
+    auto store_b = [&](int buf, int64_t jb, int64_t jend) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int e = tid + 256 * u;
+            const int kk = e / BW;
+            if (gin[u]) sB[buf][e] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+        }
+    };
+    auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
+        if (agen) sA[buf][akk * BM + arow] = A.val(rp, A.col(min(jb + akk, jend - 1)));
+    };
+
+    double acc[SVW][NSIDE][MA][NTR];
+#pragma unroll
+    for (int v = 0; v < SVW; ++v)
+#pragma unroll
+        for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+            for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+                for (int nt = 0; nt < NTR; ++nt) acc[v][sd][ma][nt] = 0.0;
+
+    int l = 0;
+    int64_t j0 = box_ptr[0], jend = box_ptr[1];
+    fetch_b(j0, jend);
+    store_b(0, j0, jend);
+    gen_a(0, j0, jend);
+    __syncthreads();
+    int buf = 0;
+    for (;;) {
+        double tw[SVW];
+#pragma unroll
+        for (int v = 0; v < SVW; ++v) tw[v] = T[static_cast<int64_t>(l) * ell + min(s_lo + v, ell - 1)];
+        int ln = l;
+        int64_t jn = j0 + KT, jendn = jend;
+        if (jn >= jend) {
+            ln = l + 1;
+            if (ln < nbox) {
+                jn = box_ptr[ln];
+                jendn = box_ptr[ln + 1];
+            }
+        }
+        const bool more = ln < nbox;
+        if (more) fetch_b(jn, jendn);
+#pragma unroll
+        for (int ks = 0; ks < KT / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[MA];
+#pragma unroll
+            for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + ma * 4 + (lane & 3)];
+            double bb[NSIDE][NTR];
+#pragma unroll
+            for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][kr * BW + sd * CW + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int v = 0; v < SVW; ++v) {
+                if (v < nsv) {
+                    double as[MA];
+#pragma unroll
+                    for (int ma = 0; ma < MA; ++ma) as[ma] = a[ma] * tw[v];
+#pragma unroll
+                    for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                        for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+                            for (int nt = 0; nt < NTR; ++nt)
+                                acc[v][sd][ma][nt] = mfma44(as[ma], bb[sd][nt], acc[v][sd][ma][nt]);
+                }
+            }
+        }
+        if (!more) break;
+        store_b(buf ^ 1, jn, jendn);
+        gen_a(buf ^ 1, jn, jendn);
+        __syncthreads();
+        buf ^= 1;
+        l = ln;
+        j0 = jn;
+        jend = jendn;
+    }
+    // epilogue: (s, side) column c -> Y_side(:, s*r + c)
+#pragma unroll
+    for (int v = 0; v < SVW; ++v) {
+        if (v >= nsv) continue;
+        const int sv = s_lo + v;
+#pragma unroll
+        for (int sd = 0; sd < NSIDE; ++sd) {
+            double* Yo = sd ? Y1 : Y0;
+#pragma unroll
+            for (int ma = 0; ma < MA; ++ma) {
+                const int64_t row = row0 + ma * 4 + (lane >> 4);
+#pragma unroll
+                for (int nt = 0; nt < NTR; ++nt) {
+                    const int c = nt * 16 + (lane & 15);
+                    if (row < n && c < r) Yo[row + static_cast<int64_t>(sv * r + c) * n] = acc[v][sd][ma][nt];
+                }
+            }
+        }
+    }
+}
+
+template <class AS>
+void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double* G0,
+                   const double* G1, int nside, double* Y0, double* Y1, hipStream_t s) {
+    const int ntr = (P.r + 15) / 16;
+    // tag columns per wave bounded by the accumulator budget (SVW*NSIDE*2*NTR doubles)
+    const int acc_per_sv = nside * 2 * ntr;
+    const int svw = std::max(1, std::min(8, 48 / acc_per_sv));
+    const int groups = (P.ell + 4 * svw - 1) / (4 * svw);
+    dim3 grid((P.n + 7) / 8, groups);
+#define BLR_SKETCH_CASE(NTRV, NSV, SVWV)                                                         \
+    hipLaunchKernelGGL((k_sketch<AS, NTRV, NSV, SVWV>), grid, dim3(256), 0, s, A, t.T, t.box_ptr, \
+                       P.b, G0, G1, P.n, P.r, P.ell, Y0, Y1)
+    if (nside == 2) {
+        switch (ntr) {
+            case 1: BLR_SKETCH_CASE(1, 2, 8); break;  // 48 / 4 = 12 -> 8
+            case 2: BLR_SKETCH_CASE(2, 2, 6); break;
+            case 3: BLR_SKETCH_CASE(3, 2, 4); break;
+            case 4: BLR_SKETCH_CASE(4, 2, 3); break;
+            case 5: BLR_SKETCH_CASE(5, 2, 2); break;
+            default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the sketch kernel");
+        }
+    } else {
+        switch (ntr) {
+            case 1: BLR_SKETCH_CASE(1, 1, 8); break;
+            case 2: BLR_SKETCH_CASE(2, 1, 8); break;
+            case 3: BLR_SKETCH_CASE(3, 1, 8); break;
+            case 4: BLR_SKETCH_CASE(4, 1, 6); break;
+            case 5: BLR_SKETCH_CASE(5, 1, 4); break;
+            default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the sketch kernel");
+        }
+    }
+#undef BLR_SKETCH_CASE
+    check_launch("tagged sketch");
 }
 
 // Calls f(src) with the entry source of the operator (or of its adjoint).
@@ -779,19 +1057,12 @@ __global__ __launch_bounds__(256) void k_scale(double a, double* __restrict__ x,
 
 void launch_sketch(const OpData& op, const PlanData& P, const DeviceTables& t, const double* G,
                    const double* H, double* Y, double* Z, hipStream_t s) {
-    const int LR = P.ell * P.r;
     if (op.type == OpType::Kernel) {
-        // A* = A: one pass over A serves Omega and Psi (2*ell*r columns).
-        TaggedB B{t.T, t.row_box, G, H, P.n, P.r, P.ell, LR};
-        SplitOut O{Y, Z, P.n, LR};
-        with_source(op, 0, [&](auto A) { gemm_launch(A, B, O, P.n, P.n, 2 * LR, s); });
+        // A* = A: one pass over A serves Omega and Psi.
+        with_source(op, 0, [&](auto A) { sketch_launch(A, P, t, G, H, 2, Y, Z, s); });
     } else {
-        TaggedB BY{t.T, t.row_box, G, G, P.n, P.r, P.ell, LR};
-        SplitOut OY{Y, Y, P.n, LR};
-        with_source(op, 0, [&](auto A) { gemm_launch(A, BY, OY, P.n, P.n, LR, s); });
-        TaggedB BZ{t.T, t.row_box, H, H, P.n, P.r, P.ell, LR};
-        SplitOut OZ{Z, Z, P.n, LR};
-        with_source(op, 1, [&](auto A) { gemm_launch(A, BZ, OZ, P.n, P.n, LR, s); });
+        with_source(op, 0, [&](auto A) { sketch_launch(A, P, t, G, G, 1, Y, Y, s); });
+        with_source(op, 1, [&](auto A) { sketch_launch(A, P, t, H, H, 1, Z, Z, s); });
     }
 }
 
