@@ -30,6 +30,31 @@ METRIC = "BLR compressions/s + operator-applies per compression at 1e-8 rel err;
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_laplace2d_n65536_fp64.md")
+KERNELS_SRC = os.path.join(ROOT, "paper_2501_05528_amd", "csrc", "kernels.hip")
+
+
+def measured_sketch_traffic(workload):
+    """HBM bytes per sketch launch from the committed rocprofv3 counter summary, or None
+    when the summary is for another workload or the kernels changed since it was taken."""
+    import hashlib
+    if workload != "laplace2d_n65536" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    rec = {}
+    for line in text.splitlines():
+        if ":" in line and not line.startswith(("|", " ")):
+            key, _, val = line.partition(":")
+            rec[key.strip()] = val.strip()
+    if rec.get("kernels.hip sha256") != sha:
+        return None
+    try:
+        return float(rec["sketch_traffic_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -120,6 +145,9 @@ def main():
     ap.add_argument("--workload", default="laplace2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB "
+                         "(a plain kernel of known traffic for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -144,6 +172,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    if args.calib_copy_mib:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
+        del src, dst
     last = handles[-1]
     err_fro = None
     if not args.no_error:
@@ -159,7 +195,8 @@ def main():
     achieved = sketch_flops / (stage["ms_sketch"] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "k_opgemm (tagged sketch, FP64 MFMA)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": measured_sketch_traffic(wl.name),
                 "algorithmic_flops_per_launch": sketch_flops}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,

@@ -451,8 +451,7 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
             HIPC(hipMemcpyAsync(h->Zhat, Zh, P.n * P.r * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
         mark(2);
-        launch_orth(P, t, Yh, h->U, nullptr, s);
-        launch_orth(P, t, Zh, h->V, nullptr, s);
+        launch_orth2(P, t, Yh, Zh, h->U, h->V, nullptr, nullptr, s);
         mark(3);
         launch_cores(o, P, t, h->U, h->V, h->Atil, s);
         mark(4);

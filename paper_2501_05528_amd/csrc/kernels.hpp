@@ -23,6 +23,9 @@ void launch_postprocess(const PlanData& P, const DeviceTables& t, const double* 
 
 void launch_orth(const PlanData& P, const DeviceTables& t, double* S, double* Q, double* sigma,
                  hipStream_t s);
+// Both sides in one launch (S1/Q1 may be null for one side).
+void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* S1, double* Q0,
+                  double* Q1, double* sig0, double* sig1, hipStream_t s);
 
 void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
                   const double* V, double* Atil, hipStream_t s);
