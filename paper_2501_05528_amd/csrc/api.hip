@@ -392,7 +392,10 @@ blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const dou
         const OpData& o = op_of(op, P);
         if (!U || !V || !Atil || !Bvals) fail(BLR_ERR_INVALID_ARG, "NULL U, V, Atil or B");
         const DeviceTables& t = plan->d->tables();
-        launch_nearfield(o, P, t, U, V, Atil, Bvals, static_cast<hipStream_t>(stream));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        AsyncTemps tmp(s);
+        double* work = tmp.get(nearfield_workspace_doubles(P));
+        launch_nearfield(o, P, t, U, V, Atil, Bvals, work, s);
     });
 }
 
@@ -455,7 +458,7 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         mark(3);
         launch_cores(o, P, t, h->U, h->V, h->Atil, s);
         mark(4);
-        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, s);
+        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, tmp.get(nearfield_workspace_doubles(P)), s);
         mark(5);
         if (timing) {
             HIPC(hipStreamSynchronize(s));

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <sstream>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -114,6 +115,14 @@ struct KernelSrc {
         double v = kval<KIND>(dx * dx + dy * dy + dz * dz);
         return a.i == b.i ? diag : v;
     }
+    // column contexts staged through LDS: 3 doubles per column
+    static constexpr int STAGE = 3;
+    __device__ void stage(int64_t j, double* c) const {
+        c[0] = px[j];
+        c[1] = py[j];
+        c[2] = pz[j];
+    }
+    __device__ P col_staged(const double* c, int64_t j) const { return P{c[0], c[1], c[2], j}; }
 };
 
 struct DenseSrc {  // A(i, j) = A[i + j*lda]
@@ -125,6 +134,9 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ double val(const P& a, const P& b) const { return A[a.i + b.i * lda]; }
+    static constexpr int STAGE = 1;
+    __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
+    __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
 };
 
 struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
@@ -136,6 +148,9 @@ struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ double val(const P& a, const P& b) const { return A[b.i + a.i * lda]; }
+    static constexpr int STAGE = 1;
+    __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
+    __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
 };
 
 // ------------------------------------------------------------ B operands
@@ -850,22 +865,190 @@ __global__ __launch_bounds__(256, (NT >= 4 ? 1 : 2)) void k_cores(AS A, const in
     }
 }
 
+// Cores for a symmetric operator (A_ji = A_ij^T): one workgroup per unordered pair i <= j
+// generates A_ij once and multiplies it by [V_j | U_j]; then
+//   Atil_ij = U_i^T (A_ij V_j)   and   Atil_ji = (V_i^T (A_ij U_j))^T,
+// the second only for i < j.  Same MFMA scheme as k_cores with 2*NT column tiles.
+template <class AS, int NT>
+__global__ __launch_bounds__(256, 2) void k_cores_sym(
+    AS A, const int64_t* __restrict__ box_ptr, const double* __restrict__ U,
+    const double* __restrict__ V, int64_t ldUV, int k, double* __restrict__ Atil, int64_t ldAt) {
+    constexpr int KT = 16, RC = 256, KP = NT * 16, NT2 = 2 * NT;
+    __shared__ double sA[KT * RC];
+    __shared__ double sV[KT * 2 * KP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = blockIdx.x, i = blockIdx.y;
+    if (i > j) return;
+    const int64_t ri0 = box_ptr[i], cj0 = box_ptr[j];
+    const int mi = static_cast<int>(box_ptr[i + 1] - ri0);
+    const int mj = static_cast<int>(box_ptr[j + 1] - cj0);
+    d4 accT[2][NT][NT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int at = 0; at < NT; ++at)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) accT[h][at][nt] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int rc0 = 0; rc0 < mi; rc0 += RC) {
+        const int grow = rc0 + tid;
+        const bool rowok = grow < mi;
+        const auto rp = A.row(ri0 + (rowok ? grow : 0));
+        d4 acc[4][NT2];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT2; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < mj; k0 += KT) {
+#pragma unroll 4
+            for (int kk = 0; kk < KT; ++kk) {
+                double v = 0.0;
+                if (rowok && k0 + kk < mj) v = A.val(rp, A.col(cj0 + k0 + kk));
+                sA[kk * RC + tid] = v;
+            }
+            for (int idx = tid; idx < KT * 2 * KP; idx += 256) {
+                const int kk = idx / (2 * KP), cc = idx - kk * 2 * KP;
+                const int h = cc / KP, c = cc - h * KP;
+                double v = 0.0;
+                if (k0 + kk < mj && c < k) v = (h ? U : V)[cj0 + k0 + kk + static_cast<int64_t>(c) * ldUV];
+                sV[idx] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < KT / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                double a[4], bb[NT2];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) a[mt] = sA[kr * RC + wave * 64 + mt * 16 + (lane & 15)];
+#pragma unroll
+                for (int nt = 0; nt < NT2; ++nt) bb[nt] = sV[kr * 2 * KP + nt * 16 + (lane & 15)];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT2; ++nt) acc[mt][nt] = mfma64(a[mt], bb[nt], acc[mt][nt]);
+            }
+            __syncthreads();
+        }
+        // accT[0](a, c) += sum_rows U_i(row, a) (A V_j)(row, c); accT[1] with V_i and A U_j
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int lrow = rc0 + wave * 64 + mt * 16 + d_row(lane, v);
+#pragma unroll
+                for (int at = 0; at < NT; ++at) {
+                    const int acol = at * 16 + (lane & 15);
+                    double ua = 0.0, va = 0.0;
+                    if (lrow < mi && acol < k) {
+                        ua = U[ri0 + lrow + static_cast<int64_t>(acol) * ldUV];
+                        va = V[ri0 + lrow + static_cast<int64_t>(acol) * ldUV];
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        accT[0][at][nt] = mfma64(ua, acc[mt][nt][v], accT[0][at][nt]);
+                        accT[1][at][nt] = mfma64(va, acc[mt][NT + nt][v], accT[1][at][nt]);
+                    }
+                }
+            }
+    }
+    for (int h = 0; h < 2; ++h) {
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int at = 0; at < NT; ++at)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int idx = (at * 16 + d_row(lane, v)) + (nt * 16 + d_col(lane)) * KP;
+                            sA[idx] = (w == 0 ? 0.0 : sA[idx]) + accT[h][at][nt][v];
+                        }
+            }
+            __syncthreads();
+        }
+        if (h == 0 || i < j) {
+            for (int idx = tid; idx < k * k; idx += 256) {
+                const int a = idx % k, c = idx / k;
+                if (h == 0)
+                    Atil[(static_cast<int64_t>(i) * k + a) + (static_cast<int64_t>(j) * k + c) * ldAt] = sA[a + c * KP];
+                else  // Atil_ji(c, a) = (V_i^T A_ij U_j)(a, c)
+                    Atil[(static_cast<int64_t>(j) * k + c) + (static_cast<int64_t>(i) * k + a) * ldAt] = sA[a + c * KP];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ near field
-// One workgroup per (box i, colour c): the probe block
-//   P_c(I_i, cols) = sum_{l' of colour c} [A_il' - U_i Atil_il' V_l'^T](:, cols)
-// restricted to the columns of the neighbour l of colour c (eq. sparse_struct_ids).
-template <class AS>
-__global__ __launch_bounds__(256) void k_nearfield(
+// Near field in two launches.  k_nf_q: for every (box i, colour c) and probe column col,
+//   Qg[(i, c)](col, t) = sum_{l' of colour c, col < m_l'} sum_s V_l'(col, s) Atil(i k + t, l' k + s)
+// i.e. Q^T = X_c^T V Atil_{i,:}^T (m_max x KP per pair, zero beyond k).  k_nf_b:
+//   B_il(a, col) = sum_{l'} A(I_i[a], I_l'[col]) - sum_t U_i(a, t) Qg(col, t).
+template <int KP>
+__global__ __launch_bounds__(256) void k_nf_q(const int64_t* __restrict__ box_ptr,
+                                              const int32_t* __restrict__ colour_ptr,
+                                              const int32_t* __restrict__ colour_boxes,
+                                              const int32_t* __restrict__ nf_pair, int ncol,
+                                              const double* __restrict__ V, int64_t ldUV,
+                                              const double* __restrict__ Atil, int64_t ldAt, int k,
+                                              int m_max, double* __restrict__ Qg) {
+    __shared__ double sAt[KP * KP];  // sAt[s * KP + t] = Atil(i k + t, l' k + s)
+    const int tid = threadIdx.x;
+    const int pair = blockIdx.x;  // (i, c)
+    const int i = pair / ncol, c = pair - (pair / ncol) * ncol;
+    if (nf_pair[pair] < 0) return;
+    const int cb0 = colour_ptr[c], cb1 = colour_ptr[c + 1];
+    double* Q = Qg + static_cast<int64_t>(pair) * m_max * KP;
+    for (int col0 = 0; col0 < m_max; col0 += 256) {
+        const int col = col0 + tid;
+        double q[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) q[t] = 0.0;
+#pragma unroll 1
+        for (int qq = cb0; qq < cb1; ++qq) {
+            const int lp = colour_boxes[qq];
+            const int64_t lp0 = box_ptr[lp];
+            const int mlp = static_cast<int>(box_ptr[lp + 1] - lp0);
+            __syncthreads();
+            for (int idx = tid; idx < KP * KP; idx += 256) {
+                const int t = idx % KP, sx = idx / KP;
+                sAt[idx] = (t < k && sx < k)
+                    ? Atil[(static_cast<int64_t>(i) * k + t) + (static_cast<int64_t>(lp) * k + sx) * ldAt] : 0.0;
+            }
+            __syncthreads();
+            if (col < mlp) {
+#pragma unroll 1
+                for (int sx = 0; sx < k; ++sx) {
+                    const double v = V[lp0 + col + static_cast<int64_t>(sx) * ldUV];
+                    const double* at = sAt + sx * KP;
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) q[t] += at[t] * v;
+                }
+            }
+        }
+        if (col < m_max) {
+#pragma unroll
+            for (int t = 0; t < KP; ++t) Q[static_cast<int64_t>(col) * KP + t] = q[t];
+        }
+    }
+}
+
+template <class AS, int KP>
+__global__ __launch_bounds__(256) void k_nf_b(
     AS A, const int64_t* __restrict__ box_ptr, const int32_t* __restrict__ near_idx,
     const int64_t* __restrict__ b_off, const int32_t* __restrict__ colour_ptr,
     const int32_t* __restrict__ colour_boxes, const int32_t* __restrict__ nf_pair, int ncol,
-    const double* __restrict__ U, const double* __restrict__ V, int64_t ldUV,
-    const double* __restrict__ Atil, int64_t ldAt, int k, double* __restrict__ Bv) {
-    constexpr int CW = 16;
-    __shared__ double sQ[64 * CW];
+    const double* __restrict__ U, int64_t ldUV, int k, int m_max, const double* __restrict__ Qg,
+    double* __restrict__ Bv) {
+    constexpr int CW = 16, NB = 32;
+    __shared__ double scol[NB * CW * AS::STAGE];
+    __shared__ int64_t sidx[NB * CW];
+    __shared__ int svalid[NB * CW];
+    __shared__ double sQ[CW * KP];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x / ncol, c = blockIdx.x - (blockIdx.x / ncol) * ncol;
-    const int p = nf_pair[static_cast<int64_t>(i) * ncol + c];
+    const int pair = blockIdx.x;
+    const int i = pair / ncol, c = pair - (pair / ncol) * ncol;
+    const int p = nf_pair[pair];
     if (p < 0) return;
     const int l = near_idx[p];
     const int64_t ri0 = box_ptr[i];
@@ -873,47 +1056,62 @@ __global__ __launch_bounds__(256) void k_nearfield(
     const int ml = static_cast<int>(box_ptr[l + 1] - box_ptr[l]);
     double* Bout = Bv + b_off[p];
     const int cb0 = colour_ptr[c], cb1 = colour_ptr[c + 1];
+    const double* Q = Qg + static_cast<int64_t>(pair) * m_max * KP;
+#pragma unroll 1
     for (int col0 = 0; col0 < ml; col0 += CW) {
         const int ncw = min(CW, ml - col0);
-        for (int idx = tid; idx < k * CW; idx += 256) {
-            const int t = idx % k, cc = idx / k;
-            double acc = 0.0;
-            if (cc < ncw) {
-                for (int q = cb0; q < cb1; ++q) {
-                    const int lp = colour_boxes[q];
-                    const int64_t lp0 = box_ptr[lp];
-                    if (col0 + cc >= box_ptr[lp + 1] - lp0) continue;
-                    const double* arow = Atil + (static_cast<int64_t>(i) * k + t) + static_cast<int64_t>(lp) * k * ldAt;
-                    const double* vrow = V + lp0 + col0 + cc;
-                    for (int s = 0; s < k; ++s) acc += arow[static_cast<int64_t>(s) * ldAt] * vrow[static_cast<int64_t>(s) * ldUV];
-                }
-            }
-            sQ[t + cc * 64] = acc;
-        }
         __syncthreads();
-        for (int a = tid; a < mi; a += 256) {
+        for (int e = tid; e < CW * KP; e += 256) {
+            const int cc = e / KP;
+            sQ[e] = (col0 + cc < m_max) ? Q[static_cast<int64_t>(col0) * KP + e] : 0.0;
+        }
+#pragma unroll 1
+        for (int a0 = 0; a0 < mi; a0 += 256) {
+            const int arow = a0 + tid;
+            const bool rowok = arow < mi;
+            const auto rp = A.row(ri0 + (rowok ? arow : 0));
             double acc[CW];
 #pragma unroll
             for (int cc = 0; cc < CW; ++cc) acc[cc] = 0.0;
-            const auto rp = A.row(ri0 + a);
-            for (int q = cb0; q < cb1; ++q) {
-                const int lp = colour_boxes[q];
-                const int64_t lp0 = box_ptr[lp];
-                const int mlp = static_cast<int>(box_ptr[lp + 1] - lp0);
+#pragma unroll 1
+            for (int qb = cb0; qb < cb1; qb += NB) {
+                const int nbq = min(NB, cb1 - qb);
+                __syncthreads();
+                for (int e = tid; e < nbq * CW; e += 256) {
+                    const int bq = e / CW, cc = e - bq * CW;
+                    const int lp = colour_boxes[qb + bq];
+                    const int64_t lp0 = box_ptr[lp];
+                    const int mlp = static_cast<int>(box_ptr[lp + 1] - lp0);
+                    const bool ok = col0 + cc < mlp;
+                    const int64_t j = lp0 + (ok ? col0 + cc : 0);
+                    A.stage(j, scol + e * AS::STAGE);
+                    sidx[e] = j;
+                    svalid[e] = ok ? 1 : 0;
+                }
+                __syncthreads();
+#pragma unroll 1
+                for (int bq = 0; bq < nbq; ++bq) {
+#pragma unroll
+                    for (int cc = 0; cc < CW; ++cc) {
+                        const int e = bq * CW + cc;
+                        const double v = A.val(rp, A.col_staged(scol + e * AS::STAGE, sidx[e]));
+                        acc[cc] += svalid[e] ? v : 0.0;
+                    }
+                }
+            }
+            if (rowok) {
+                const double* ur = U + ri0 + arow;
+#pragma unroll 1
+                for (int t = 0; t < k; ++t) {
+                    const double u = ur[static_cast<int64_t>(t) * ldUV];
+#pragma unroll
+                    for (int cc = 0; cc < CW; ++cc) acc[cc] -= u * sQ[cc * KP + t];
+                }
 #pragma unroll
                 for (int cc = 0; cc < CW; ++cc)
-                    if (cc < ncw && col0 + cc < mlp) acc[cc] += A.val(rp, A.col(lp0 + col0 + cc));
+                    if (cc < ncw) Bout[arow + static_cast<int64_t>(col0 + cc) * mi] = acc[cc];
             }
-            for (int s = 0; s < k; ++s) {
-                const double u = U[ri0 + a + static_cast<int64_t>(s) * ldUV];
-#pragma unroll
-                for (int cc = 0; cc < CW; ++cc) acc[cc] -= u * sQ[s + cc * 64];
-            }
-#pragma unroll
-            for (int cc = 0; cc < CW; ++cc)
-                if (cc < ncw) Bout[a + static_cast<int64_t>(col0 + cc) * mi] = acc[cc];
         }
-        __syncthreads();
     }
 }
 
@@ -1178,6 +1376,17 @@ void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, co
     const int64_t ldAt = static_cast<int64_t>(P.b) * P.k;
     dim3 grid(P.b, P.b);
     const int nt = (P.k + 15) / 16;
+    if (op.type == OpType::Kernel && nt <= 2) {
+        with_source(op, 0, [&](auto A) {
+            using AS = decltype(A);
+            switch (nt) {
+                case 1: hipLaunchKernelGGL((k_cores_sym<AS, 1>), grid, dim3(256), 0, s, A, t.box_ptr, U, V, P.n, P.k, Atil, ldAt); break;
+                default: hipLaunchKernelGGL((k_cores_sym<AS, 2>), grid, dim3(256), 0, s, A, t.box_ptr, U, V, P.n, P.k, Atil, ldAt); break;
+            }
+        });
+        check_launch("cores");
+        return;
+    }
     with_source(op, 0, [&](auto A) {
         using AS = decltype(A);
         switch (nt) {
@@ -1190,16 +1399,33 @@ void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, co
     check_launch("cores");
 }
 
+int64_t nearfield_workspace_doubles(const PlanData& P) {
+    const int64_t kp = 16 * ((P.k + 15) / 16);
+    return static_cast<int64_t>(P.b) * P.ncol * P.m_max * kp;
+}
+
 void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
-                      const double* V, const double* Atil, double* Bv, hipStream_t s) {
+                      const double* V, const double* Atil, double* Bv, double* work, hipStream_t s) {
     if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "k > 64 is not supported by the near-field kernel");
     const int64_t ldAt = static_cast<int64_t>(P.b) * P.k;
-    with_source(op, 0, [&](auto A) {
-        using AS = decltype(A);
-        hipLaunchKernelGGL((k_nearfield<AS>), dim3(P.b * P.ncol), dim3(256), 0, s, A, t.box_ptr,
-                           t.near_idx, t.b_off, t.colour_ptr, t.colour_boxes, t.nf_pair, P.ncol, U,
-                           V, P.n, Atil, ldAt, P.k, Bv);
-    });
+    const int kp = 16 * ((P.k + 15) / 16);
+    const dim3 grid(P.b * P.ncol);
+    auto run = [&](auto kpc) {
+        constexpr int KP = decltype(kpc)::value;
+        hipLaunchKernelGGL((k_nf_q<KP>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes,
+                           t.nf_pair, P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work);
+        with_source(op, 0, [&](auto A) {
+            using AS = decltype(A);
+            hipLaunchKernelGGL((k_nf_b<AS, KP>), grid, dim3(256), 0, s, A, t.box_ptr, t.near_idx, t.b_off,
+                               t.colour_ptr, t.colour_boxes, t.nf_pair, P.ncol, U, P.n, P.k, P.m_max, work, Bv);
+        });
+    };
+    switch (kp) {
+        case 16: run(std::integral_constant<int, 16>{}); break;
+        case 32: run(std::integral_constant<int, 32>{}); break;
+        case 48: run(std::integral_constant<int, 48>{}); break;
+        default: run(std::integral_constant<int, 64>{}); break;
+    }
     check_launch("near field");
 }
 

@@ -30,8 +30,10 @@ void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* 
 void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
                   const double* V, double* Atil, hipStream_t s);
 
+// Near field; work must hold nearfield_workspace_doubles(P) doubles.
+int64_t nearfield_workspace_doubles(const PlanData& P);
 void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
-                      const double* V, const double* Atil, double* Bv, hipStream_t s);
+                      const double* V, const double* Atil, double* Bv, double* work, hipStream_t s);
 
 // y = A_uBLR x (or its transpose); work must hold 2 * b*k*ncols + nsplit*b*k*ncols doubles
 // (see apply_workspace_doubles).
