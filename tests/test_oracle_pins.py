@@ -206,6 +206,38 @@ def test_p6_cores_and_nearfield_vs_dense(planted):
         assert np.allclose(Bij, ref, atol=1e-12)
 
 
+def test_p6_nearfield_leakage_closed_form():
+    """For a matrix that is not of exact rank, the probe of colour c picks up the far-field
+    truncation residuals of every box of colour c (Table 1, near field by probing):
+    B_ij = sum over boxes l of colour(j) of (A_il - U_i Atil_il V_l*)[:, :m_j], by dense
+    slicing on a ragged jittered grid (boxes of unequal size)."""
+    g = W.grid_geometry(2, (7, 6), (6, 5), jitter=0.3, seed=11)
+    k, p = 8, 6
+    op = O.KernelOperator("log", g.pts)
+    A = op.block()
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(5, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(5, g.n, k + p)
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, k, p, 3, T, G, H)
+    bp, U, V, At, col = g.box_ptr, res["U"], res["V"], res["Atil"], res["colour"]
+    leak = 0.0
+    for (i, j), Bij in res["B"].items():
+        ri = slice(bp[i], bp[i + 1])
+        ref = np.zeros_like(Bij)
+        for l in range(g.nboxes):
+            if col[l] != col[j]:
+                continue
+            cl = slice(bp[l], bp[l + 1])
+            R = A[ri, cl] - U[ri] @ At[i * k:(i + 1) * k, l * k:(l + 1) * k] @ V[cl].T
+            w = min(R.shape[1], Bij.shape[1])
+            ref[:, :w] += R[:, :w]
+            if l != j:
+                leak = max(leak, np.max(np.abs(R)))
+        assert np.max(np.abs(Bij - ref)) <= 1e-12 * np.max(np.abs(A)), (i, j)
+    assert leak > 1e-8          # the far residuals are really there in this case
+
+
 def test_p6_apply_equals_matrix_for_exact_rank(planted):
     g, A, res, k = planted["g"], planted["A"], planted["res"], planted["wl"].k
     x = np.random.default_rng(0).standard_normal((g.n, 3))
