@@ -17,11 +17,14 @@ admissibility   near/far lists and probe colours (Section 2.5, Section 6.1)
 operators       black-box operators: dense matrix and kernel matrices
 tagging         Alg. 2 (tagging) with the aspect-ratio optimisation of Section 5.3
 reconstruct     steps (II)-(III) of Table 1, the uBLR apply, error metrics
+refine          mixed-precision tagging with one FP64 refinement sketch (not in the paper)
 """
-from . import admissibility, operators, tagging, reconstruct  # noqa: F401
+from . import admissibility, operators, tagging, reconstruct, refine  # noqa: F401
 from .admissibility import near_lists, far_lists, colours, num_tag_columns  # noqa: F401
 from .operators import DenseOperator, KernelOperator, CountingOperator  # noqa: F401
 from .tagging import (extended_test_matrix, null_space, projected_tags, aspect_ratio,  # noqa: F401
                       optimise_tag_vector, tag_plan, tag_postprocess, col_topk, tag_bases)
 from .reconstruct import (cores, nearfield_probes, ublr_apply, dense_reconstruction,  # noqa: F401
                           rel_fro_error, power_norm_estimate, reconstruct_tag)
+from .refine import (sample_basis, sample_bases, mixed_test_blocks, far_sample,  # noqa: F401
+                     refine_bases, reconstruct_tag_refined)

@@ -397,3 +397,131 @@ def test_p9_errors_fro_and_power():
     est = O.power_norm_estimate(lambda v: E @ v, lambda v: E.T @ v, g.n, x0, 20)
     true = np.linalg.norm(E, 2)
     assert est <= true * (1 + 1e-12) and est >= 0.9 * true
+
+
+# ---------------------------------------------------------------- P11 mixed-precision refinement
+def test_p11_far_sample_vs_masked_dense():
+    """far_sample = (A with every near block zeroed) X, by an elementwise block mask on the
+    dense matrix (both orientations), on a ragged jittered grid."""
+    g = W.grid_geometry(2, (5, 4), (4, 3), jitter=0.3, seed=4)
+    A = O.KernelOperator("exp", g.pts).block()
+    A = A + 0.1 * np.random.default_rng(1).standard_normal(A.shape)   # make it nonsymmetric
+    op = O.DenseOperator(A)
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    rb = np.repeat(np.arange(g.nboxes), np.diff(g.box_ptr))
+    mask = np.ones_like(A)
+    for i in range(g.nboxes):
+        for j in near[i]:
+            mask[np.ix_(rb == i, rb == j)] = 0.0
+    X = np.random.default_rng(2).standard_normal((g.n, 5))
+    assert np.allclose(O.far_sample(op, X, g.box_ptr, far), (A * mask) @ X, atol=1e-13)
+    assert np.allclose(O.far_sample(op, X, g.box_ptr, far, adjoint=True), (A * mask).T @ X, atol=1e-13)
+
+
+def test_p11_sample_basis_spans_and_signs():
+    S = np.random.default_rng(3).standard_normal((30, 7)) @ np.diag(10.0 ** -np.arange(7))
+    Q = O.sample_basis(S)
+    assert np.allclose(Q.T @ Q, np.eye(7), atol=1e-14)
+    assert np.allclose(Q @ (Q.T @ S), S, atol=1e-14)
+    for c in range(7):
+        assert Q[np.argmax(np.abs(Q[:, c])), c] > 0
+
+
+def test_p11_refinement_recovers_exact_rank_from_perturbed_bases(planted):
+    """For an exact-rank far field, any r_lo-column starting bases whose span holds the
+    true column spaces up to a perturbation give exact bases after the refinement: the
+    far-field samples are exact FP64 products, so their range is the true U_i."""
+    g, A, wl = planted["g"], planted["A"], planted["wl"]
+    k, bp = wl.k, g.box_ptr
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    r_lo, r = k + 6, k + 4
+    rng = np.random.default_rng(5)
+    U0 = np.zeros((g.n, r_lo))
+    V0 = np.zeros((g.n, r_lo))
+    for i in range(g.nboxes):
+        rows = slice(bp[i], bp[i + 1])
+        m = bp[i + 1] - bp[i]
+        for Q0, tru in ((U0, planted["us"][i]), (V0, planted["vs"][i])):
+            X = np.hstack([tru + 1e-3 * rng.standard_normal(tru.shape), rng.standard_normal((m, r_lo - k))])
+            Q0[rows] = O.sample_basis(X)
+    gu, gv = W.refinement_gammas(9, g.nboxes, r_lo, r)
+    U, V, _, _ = O.refine_bases(O.DenseOperator(A), U0, V0, gu, gv, bp, far, k)
+    for i in range(g.nboxes):
+        rows = slice(bp[i], bp[i + 1])
+        us, vs = planted["us"][i], planted["vs"][i]
+        assert np.linalg.norm(U[rows] @ U[rows].T - us @ us.T, 2) <= 1e-11
+        assert np.linalg.norm(V[rows] @ V[rows].T - vs @ vs.T, 2) <= 1e-11
+
+
+def test_p11_refined_pipeline_exact_rank(planted):
+    g, A, wl = planted["g"], planted["A"], planted["wl"]
+    k, bp = wl.k, g.box_ptr
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    r_lo = k + 10
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, r_lo)
+    gu, gv = W.refinement_gammas(wl.seed, g.nboxes, r_lo, k + wl.p)
+    op = O.DenseOperator(A)
+    res = O.reconstruct_tag_refined(op, bp, g.lattice, k, wl.p, 3, T, G, H, gu, gv)
+    assert O.rel_fro_error(op, res["U"], res["V"], res["Atil"], res["B"], bp, k) <= 1e-12
+
+
+def test_p11_refinement_no_worse_than_plain_tagging():
+    """A half-step of subspace iteration: on the log kernel the refined bases are at least
+    as accurate as plain tagging with the same sketch width (same seeds)."""
+    g = W.grid_geometry(2, 5, 8)
+    k, p = 12, 8
+    op = O.DenseOperator(O.KernelOperator("log", g.pts).block())
+    near = O.near_lists(g.lattice)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(21, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(21, g.n, k + p)
+    plain = O.reconstruct_tag(op, g.box_ptr, g.lattice, k, p, 3, T, G, H)
+    gu, gv = W.refinement_gammas(21, g.nboxes, k + p, k + p)
+    ref = O.reconstruct_tag_refined(op, g.box_ptr, g.lattice, k, p, 3, T, G, H, gu, gv)
+    e0 = O.rel_fro_error(op, plain["U"], plain["V"], plain["Atil"], plain["B"], g.box_ptr, k)
+    e1 = O.rel_fro_error(op, ref["U"], ref["V"], ref["Atil"], ref["B"], g.box_ptr, k)
+    assert e1 <= 1.05 * e0, (e0, e1)
+
+
+def test_p11_each_side_uses_the_other_sides_basis():
+    """U_i comes from the far block row applied to blocks of V0 (and V_j from the block
+    column applied to blocks of U0): with good V0 and U0 orthogonal to V0 (useless as a
+    test space for the far block row) the U side still meets
+    the brute-force bound ||F_i - U_i U_i* F_i||_2 <= 10 sigma_{k+1}(F_i), on a
+    nonsymmetric matrix."""
+    g = W.grid_geometry(2, 5, 8)
+    k, p = 10, 8
+    r_lo = k + p
+    K = O.KernelOperator("log", g.pts).block()
+    x = g.pts[:, 0]
+    A = K + np.outer(np.cos(3 * x), np.sin(2 * x))          # nonsymmetric, far blocks stay low rank
+    op = O.DenseOperator(A)
+    bp = g.box_ptr
+    near = O.near_lists(g.lattice)
+    far = O.far_lists(near, g.nboxes)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(31, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(31, g.n, r_lo)
+    z, _ = O.tag_plan(T, near, far)
+    _, Z = O.tagging.sketch(op, T, G, H, bp)
+    V0 = O.sample_bases(O.tag_postprocess(Z, z, bp, r_lo), bp)
+    # U0 deliberately useless for the U side: orthogonal to V0 in every box
+    U0 = np.zeros_like(V0)
+    rng = np.random.default_rng(6)
+    for i in range(g.nboxes):
+        rows = slice(bp[i], bp[i + 1])
+        X = rng.standard_normal((bp[i + 1] - bp[i], r_lo))
+        U0[rows] = O.sample_basis(X - V0[rows] @ (V0[rows].T @ X))
+    gu, gv = W.refinement_gammas(31, g.nboxes, r_lo, k + p)
+    U, _, _, _ = O.refine_bases(op, U0, V0, gu, gv, bp, far, k)
+    for i in range(g.nboxes):
+        ri = slice(bp[i], bp[i + 1])
+        cols = np.concatenate([np.arange(bp[l], bp[l + 1]) for l in far[i]])
+        F = A[ri][:, cols]
+        s = np.linalg.svd(F, compute_uv=False)
+        Ui = U[ri]
+        assert np.linalg.norm(F - Ui @ (Ui.T @ F), 2) <= 10 * s[k], i

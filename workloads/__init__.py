@@ -32,6 +32,8 @@ STREAM_JITTER = 4
 STREAM_ARRIVALS = 5
 STREAM_POWER = 6
 STREAM_JOBS = 7
+STREAM_GAMMA_U = 8
+STREAM_GAMMA_V = 9
 
 
 def rng(seed: int, stream: int) -> np.random.Generator:
@@ -119,6 +121,16 @@ def tag_matrix(seed: int, nboxes: int, ell: int) -> np.ndarray:
 def gaussian_test_blocks(seed: int, n: int, r: int):
     """The stacked per-box Gaussian blocks G = [G_1; ...; G_b] and H (each N x r)."""
     return gaussian_colmajor(seed, STREAM_G, n, r), gaussian_colmajor(seed, STREAM_H, n, r)
+
+
+def refinement_gammas(seed: int, nboxes: int, r_lo: int, r: int):
+    """Per-box r_lo x r Gaussian mixing blocks (b x r_lo x r each) for the refinement
+    sketch of the mixed-precision mode: (gamma_u, gamma_v), C-ordered, so that the flat
+    device layout holds entry (a, c) of block l at (l*r_lo + a)*r + c."""
+    gu = gaussian_colmajor(seed, STREAM_GAMMA_U, nboxes * r_lo, r)
+    gv = gaussian_colmajor(seed, STREAM_GAMMA_V, nboxes * r_lo, r)
+    return (np.ascontiguousarray(gu.reshape(nboxes, r_lo, r)),
+            np.ascontiguousarray(gv.reshape(nboxes, r_lo, r)))
 
 
 def planted_exact_rank(geom: Geometry, k: int, seed: int):
