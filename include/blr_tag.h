@@ -226,34 +226,106 @@ blr_status blr_cores(const blr_plan* plan, const blr_operator* op, const double*
 blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const double* U,
                          const double* V, const double* Atil, double* Bvals, void* stream);
 
+/*
+ * Mixed modes, step 1: the tagged sketches of Alg. 2 with r_lo columns per tag
+ * column in low precision (precision = BLR_PREC_FP32_REFINE or
+ * BLR_PREC_BF16_REFINE): kernel entries in FP32 (dense operators: A rounded to
+ * FP32), each entry scaled by T(i, j) in FP32 and rounded to the MFMA type,
+ * G and H rounded likewise, FP32 accumulation.  G, H: N x r_lo (ld N);
+ * Y0, Z0: float N x ell r_lo (ld N).  Returns BLR_ERR_UNSUPPORTED for r_lo > 80.
+ */
+blr_status blr_sketch_lowp(const blr_plan* plan, const blr_operator* op, int32_t precision,
+                           int32_t r_lo, const double* G, const double* H, float* Y0, float* Z0,
+                           void* stream);
+
+/*
+ * Mixed modes, post-processing of the FP32 sketches (eq. projected_tags, in
+ * FP64): Yhat0(I_i,:) = sum_j z^(i)_j Y0(I_i, (j-1)r_lo+1 : j r_lo), N x r_lo.
+ * Either side may be NULL (input and output together).
+ */
+blr_status blr_tag_postprocess_lowp(const blr_plan* plan, int32_t r_lo, const float* Y0,
+                                    const float* Z0, double* Yhat0, double* Zhat0, void* stream);
+
+/*
+ * Orthonormal bases of per-box samples: for every box the m_i x ncols block
+ * of S (ncols <= m_min, <= 128) is factored by Householder QR in FP64 and Q
+ * receives the Q factor's ncols columns, each signed so that its entry of
+ * largest magnitude (lowest row on ties) is positive.  S is overwritten.
+ */
+blr_status blr_sample_bases(const blr_plan* plan, int32_t ncols, double* S, double* Q, void* stream);
+
+/*
+ * Mixed modes, step 3 (FP64 refinement sketch on the far field):
+ *   SY(I_i) = sum_{l in F_i} A(I_i, I_l) V0(I_l) gamma_v[l],
+ *   SZ(I_i) = sum_{l in F_i} A(I_l, I_i)* U0(I_l) gamma_u[l],
+ * U0, V0: N x r_lo; gamma_u, gamma_v: b x r_lo x r C-ordered (see
+ * blr_compress_opts); SY, SZ: N x r.  All device memory.
+ */
+blr_status blr_refine_sketch(const blr_plan* plan, const blr_operator* op, int32_t r_lo,
+                             const double* U0, const double* V0, const double* gamma_u,
+                             const double* gamma_v, double* SY, double* SZ, void* stream);
+
 /* ------------------------------------------------------------ compression */
+/*
+ * Precision of step (I).  The mixed modes are not in the paper (which runs
+ * every step in one precision):
+ *   1. the tagged sketches of Alg. 2 are taken with r_lo = k + p_lo columns
+ *      per tag column, kernel entries in FP32, contracted on FP32 or BF16 MFMA
+ *      with FP32 accumulation, and stored in FP32;
+ *   2. FP64 tag post-processing and FP64 Householder QR give orthonormal
+ *      bases U0_i, V0_i of all r_lo sample columns;
+ *   3. one FP64 refinement sketch on the far field: with the caller's r_lo x r
+ *      Gaussian blocks gamma_v[l], gamma_u[l],
+ *        SY(I_i) = sum_{l in F_i} A_il V0_l gamma_v[l],
+ *        SZ(I_i) = sum_{l in F_i} A_li* U0_l gamma_u[l],
+ *      and U_i = col(SY(I_i), k), V_i = col(SZ(I_i), k) (as in Alg. 2);
+ *   4. steps (II)-(III) of Table 1 in FP64, unchanged.
+ * Step 3 uses block-sparse products with A (2 b r columns for a black box).
+ */
 typedef enum blr_precision {
-    BLR_PREC_FP64 = 0 /* every stage in FP64 */
+    BLR_PREC_FP64 = 0,        /* every stage in FP64 */
+    BLR_PREC_FP32_REFINE = 1, /* step (I) on FP32 MFMA, then the FP64 refinement sketch */
+    BLR_PREC_BF16_REFINE = 2  /* step (I) on BF16 MFMA (FP32 accumulation), then refinement */
 } blr_precision;
 
 typedef struct blr_compress_opts {
     int32_t precision;          /* blr_precision */
-    int32_t keep_intermediates; /* 1: keep Y, Z, Yhat, Zhat in the handle for inspection */
+    int32_t keep_intermediates; /* 1: keep the sketches, samples and sample bases for inspection */
+    int32_t r_lo;               /* mixed modes: columns of G and H (k + p_lo, <= m_min, <= 80);
+                                   0 means r; ignored in FP64 */
+    int32_t reserved;           /* must be 0 */
+    /* mixed modes: device arrays b x r_lo x r, C-ordered (entry (a, c) of box l
+       at (l*r_lo + a)*r + c): gamma_v mixes V0 for the U side, gamma_u mixes U0
+       for the V side.  Ignored in FP64. */
+    const double* gamma_u;
+    const double* gamma_v;
 } blr_compress_opts;
 
 typedef struct blr_report {
-    /* stage times (ms, device events on the stream) */
+    /* stage times (ms, device events on the stream); in the mixed modes
+       ms_sketch and ms_postprocess cover the low-precision sketch */
     double ms_sketch, ms_postprocess, ms_orth, ms_cores, ms_nearfield, ms_total;
-    /* products in the paper's convention (columns applied to A and to A*) */
+    /* products in the paper's convention (columns applied to A and to A*);
+       the mixed modes add the refinement's b r block-sparse columns per side */
     int64_t applies_A, applies_At;
-    /* algorithmic work of the sketch launch */
+    /* algorithmic work of the sketch launch (4 N^2 ell r, or 4 N^2 ell r_lo) */
     double sketch_flops;
     /* aspect ratios of the plan */
     double rho_min, rho_median, rho_max;
+    /* mixed modes: sample bases + mixing + refinement sketch (ms), the
+       refinement's algorithmic work (4 r sum_i m_i |F_i|-block flops), the
+       precision and r_lo used; zero in FP64 */
+    double ms_refine, refine_flops;
+    int32_t precision, r_lo;
 } blr_report;
 
 /*
  * Full compression reconstruct_tag (Table 1): steps (I)-(III).  G and H
- * (device, N x r column-major, ld N) are the stacked Gaussian blocks G_i,
- * H_i of Alg. 2 drawn by the caller.  opts may be NULL (FP64, no
- * intermediates).  On success *out owns device U, V (N x k), Atil
- * (bk x bk) and B (b_values doubles); it keeps a reference to the plan.
- * If rep is non-NULL the call synchronises the stream and fills it.
+ * (device, N x r column-major, ld N; N x r_lo in the mixed modes) are the
+ * stacked Gaussian blocks G_i, H_i of Alg. 2 drawn by the caller.  opts may
+ * be NULL (FP64, no intermediates).  On success *out owns device U, V
+ * (N x k), Atil (bk x bk) and B (b_values doubles); it keeps a reference to
+ * the plan.  If rep is non-NULL the call synchronises the stream and fills it.
  */
 blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
                             const double* H, const blr_compress_opts* opts, void* stream,
@@ -268,12 +340,19 @@ typedef enum blr_ublr_part {
     BLR_PART_B = 3,     /* b_values */
     BLR_PART_Y = 4,     /* N x ell r   (keep_intermediates only) */
     BLR_PART_Z = 5,     /* N x ell r   (keep_intermediates only) */
-    BLR_PART_YHAT = 6,  /* N x r       (keep_intermediates only) */
-    BLR_PART_ZHAT = 7   /* N x r       (keep_intermediates only) */
+    BLR_PART_YHAT = 6,  /* N x r  (N x r_lo in the mixed modes)  (keep_intermediates only) */
+    BLR_PART_ZHAT = 7,  /* N x r  (N x r_lo in the mixed modes)  (keep_intermediates only) */
+    BLR_PART_Y0 = 8,    /* float, N x ell r_lo: low-precision sketch  (mixed, keep_intermediates) */
+    BLR_PART_Z0 = 9,    /* float, N x ell r_lo                        (mixed, keep_intermediates) */
+    BLR_PART_U0 = 10,   /* N x r_lo sample bases                      (mixed, keep_intermediates) */
+    BLR_PART_V0 = 11,   /* N x r_lo                                   (mixed, keep_intermediates) */
+    BLR_PART_SY = 12,   /* N x r refinement samples                   (mixed, keep_intermediates) */
+    BLR_PART_SZ = 13    /* N x r                                      (mixed, keep_intermediates) */
 } blr_ublr_part;
 
-/* Device pointer and element count of one part (the handle keeps ownership). */
-blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const double** ptr, int64_t* count);
+/* Device pointer and element count of one part (the handle keeps ownership);
+ * elements are double except for BLR_PART_Y0 and BLR_PART_Z0 (float). */
+blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count);
 
 /*
  * y = A_uBLR x = U (Atil (V* x)) + B x (trans = 0) or A_uBLR* x (trans = 1)

@@ -7,7 +7,9 @@ The compute path is the HIP library ``libblrtag.so`` (C ABI in
 with ``python -m paper_2501_05528_amd.build``.
 """
 from .api import (BlrError, Operator, Plan, UBLR, colmajor, colmajor_empty, compress,  # noqa: F401
-                  cores, nearfield, orthonormalize, postprocess, sketch, tag_columns)
+                  cores, nearfield, orthonormalize, postprocess, postprocess_lowp, refine_sketch,
+                  sample_bases, sketch, sketch_lowp, tag_columns)
 
 __all__ = ["BlrError", "Operator", "Plan", "UBLR", "colmajor", "colmajor_empty", "compress",
-           "cores", "nearfield", "orthonormalize", "postprocess", "sketch", "tag_columns"]
+           "cores", "nearfield", "orthonormalize", "postprocess", "postprocess_lowp",
+           "refine_sketch", "sample_bases", "sketch", "sketch_lowp", "tag_columns"]

@@ -34,14 +34,20 @@ class PlanInfo(ctypes.Structure):
 
 
 class CompressOpts(ctypes.Structure):
-    _fields_ = [("precision", c_int32), ("keep_intermediates", c_int32)]
+    _fields_ = [("precision", c_int32), ("keep_intermediates", c_int32), ("r_lo", c_int32),
+                ("reserved", c_int32), ("gamma_u", c_void_p), ("gamma_v", c_void_p)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("ms_sketch", c_double), ("ms_postprocess", c_double), ("ms_orth", c_double),
                 ("ms_cores", c_double), ("ms_nearfield", c_double), ("ms_total", c_double),
                 ("applies_A", c_int64), ("applies_At", c_int64), ("sketch_flops", c_double),
-                ("rho_min", c_double), ("rho_median", c_double), ("rho_max", c_double)]
+                ("rho_min", c_double), ("rho_median", c_double), ("rho_max", c_double),
+                ("ms_refine", c_double), ("refine_flops", c_double), ("precision", c_int32),
+                ("r_lo", c_int32)]
+
+
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
 # name -> (restype, argtypes); every symbol declared in include/blr_tag.h
@@ -66,6 +72,13 @@ SIGNATURES = {
     "blr_cores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "blr_nearfield": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p]),
+    "blr_sketch_lowp": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p]),
+    "blr_tag_postprocess_lowp": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_void_p]),
+    "blr_sample_bases": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "blr_refine_sketch": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p]),
     "blr_tag_compress": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CompressOpts),
                                    c_void_p, POINTER(c_void_p), POINTER(Report)]),
     "blr_ublr_destroy": (None, [c_void_p]),

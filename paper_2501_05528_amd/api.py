@@ -15,7 +15,9 @@ from . import _lib
 from ._lib import BlrError, check, lib  # noqa: F401
 
 KERNELS = {"log": 0, "inv_r": 1, "exp": 2, "cos": 3}
-PARTS = {"U": 0, "V": 1, "Atil": 2, "B": 3, "Y": 4, "Z": 5, "Yhat": 6, "Zhat": 7}
+PARTS = {"U": 0, "V": 1, "Atil": 2, "B": 3, "Y": 4, "Z": 5, "Yhat": 6, "Zhat": 7,
+         "Y0": 8, "Z0": 9, "U0": 10, "V0": 11, "SY": 12, "SZ": 13}
+PRECISIONS = dict(_lib.PRECISION)
 
 
 def _torch():
@@ -23,9 +25,9 @@ def _torch():
     return torch
 
 
-def colmajor_empty(rows: int, cols: int, device=None):
+def colmajor_empty(rows: int, cols: int, device=None, dtype=None):
     torch = _torch()
-    return torch.empty((cols, rows), dtype=torch.float64, device=device or "cuda").t()
+    return torch.empty((cols, rows), dtype=dtype or torch.float64, device=device or "cuda").t()
 
 
 def colmajor(a, device=None):
@@ -40,16 +42,16 @@ def colmajor(a, device=None):
 
 
 class _DeviceView:
-    """Column-major (rows x cols) float64 device memory owned by the library."""
+    """Column-major (rows x cols) float64 (or float32) device memory owned by the library."""
 
-    def __init__(self, ptr: int, rows: int, cols: int):
-        self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": "<f8",
+    def __init__(self, ptr: int, rows: int, cols: int, itemsize: int = 8):
+        self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": f"<f{itemsize}",
                                          "data": (ptr, False), "version": 2,
-                                         "strides": (8, 8 * rows)}
+                                         "strides": (itemsize, itemsize * rows)}
 
 
 def colmajor_copy(t):
-    out = colmajor_empty(t.shape[0], t.shape[1], t.device)
+    out = colmajor_empty(t.shape[0], t.shape[1], t.device, t.dtype)
     out.copy_(t)
     return out
 
@@ -174,9 +176,11 @@ class Operator:
 class UBLR:
     """Compressed A ~ U Atil V* + B owned by the library."""
 
-    def __init__(self, handle, plan: Plan):
+    def __init__(self, handle, plan: Plan, precision: str = "fp64", r_lo: int = 0):
         self._h = handle
         self.plan = plan
+        self.precision = precision
+        self.r_lo = r_lo or plan.r
 
     def part_ptr(self, name: str):
         ptr = c_void_p()
@@ -189,10 +193,14 @@ class UBLR:
         torch = _torch()
         ptr, cnt = self.part_ptr(name)
         n, k, r, ell, b = self.plan.n, self.plan.k, self.plan.r, self.plan.ell, self.plan.b
+        rs = self.r_lo if self.precision != "fp64" else r
         shapes = {"U": (n, k), "V": (n, k), "Atil": (b * k, b * k), "B": (cnt, 1),
-                  "Y": (n, ell * r), "Z": (n, ell * r), "Yhat": (n, r), "Zhat": (n, r)}
+                  "Y": (n, ell * r), "Z": (n, ell * r), "Yhat": (n, rs), "Zhat": (n, rs),
+                  "Y0": (n, ell * rs), "Z0": (n, ell * rs), "U0": (n, rs), "V0": (n, rs),
+                  "SY": (n, r), "SZ": (n, r)}
         rows, cols = shapes[name]
-        view = torch.as_tensor(_DeviceView(ptr, rows, cols), device="cuda")
+        itemsize = 4 if name in ("Y0", "Z0") else 8
+        view = torch.as_tensor(_DeviceView(ptr, rows, cols, itemsize), device="cuda")
         return view.clone(memory_format=torch.preserve_format) if cols == 1 else \
             colmajor_copy(view)
 
@@ -220,14 +228,26 @@ class UBLR:
 
 
 def compress(plan: Plan, op: Operator, G, H, keep_intermediates: bool = False, report: bool = True,
-             stream=None):
-    """reconstruct_tag (Table 1).  Returns (UBLR, report dict or None)."""
-    opts = _lib.CompressOpts(0, 1 if keep_intermediates else 0)
+             stream=None, precision: str = "fp64", gamma_u=None, gamma_v=None):
+    """reconstruct_tag (Table 1).  Returns (UBLR, report dict or None).
+
+    precision "fp32" / "bf16" selects a mixed mode: G and H are N x r_lo (r_lo =
+    their column count) and gamma_u, gamma_v are C-contiguous CUDA float64 tensors
+    b x r_lo x r for the refinement sketch."""
+    mixed = precision != "fp64"
+    r_lo = G.shape[1] if mixed else 0
+    if mixed:
+        for g in (gamma_u, gamma_v):
+            if g is None or not g.is_contiguous() or tuple(g.shape) != (plan.b, r_lo, plan.r):
+                raise ValueError(f"gamma blocks must be contiguous {plan.b} x {r_lo} x {plan.r}")
+    opts = _lib.CompressOpts(PRECISIONS[precision], 1 if keep_intermediates else 0, r_lo, 0,
+                             _ptr(gamma_u).value if mixed else None,
+                             _ptr(gamma_v).value if mixed else None)
     h = c_void_p()
     rep = _lib.Report()
     check(lib().blr_tag_compress(plan._h, op._h, _ptr(G), _ptr(H), byref(opts), _stream(stream),
                                  byref(h), byref(rep) if report else None))
-    out = UBLR(h, plan)
+    out = UBLR(h, plan, precision, r_lo)
     rd = {f: getattr(rep, f) for f, _ in _lib.Report._fields_} if report else None
     return out, rd
 
@@ -269,3 +289,40 @@ def nearfield(plan: Plan, op: Operator, U, V, Atil, stream=None):
     Bv = torch.empty(plan.info["b_values"], dtype=torch.float64, device=U.device)
     check(lib().blr_nearfield(plan._h, op._h, _ptr(U), _ptr(V), _ptr(Atil), _ptr(Bv), _stream(stream)))
     return Bv
+
+
+# ---------------------------------------------------------------- mixed-precision stages
+def sketch_lowp(plan: Plan, op: Operator, precision: str, G, H, stream=None):
+    """Low-precision tagged sketches (FP32 results, N x ell r_lo each)."""
+    torch = _torch()
+    r_lo = G.shape[1]
+    LR = plan.ell * r_lo
+    Y = colmajor_empty(plan.n, LR, G.device, torch.float32)
+    Z = colmajor_empty(plan.n, LR, G.device, torch.float32)
+    check(lib().blr_sketch_lowp(plan._h, op._h, PRECISIONS[precision], r_lo, _ptr(G), _ptr(H),
+                                _ptr(Y), _ptr(Z), _stream(stream)))
+    return Y, Z
+
+
+def postprocess_lowp(plan: Plan, r_lo: int, Y0, Z0, stream=None):
+    Yh = colmajor_empty(plan.n, r_lo, Y0.device)
+    Zh = colmajor_empty(plan.n, r_lo, Z0.device)
+    check(lib().blr_tag_postprocess_lowp(plan._h, r_lo, _ptr(Y0), _ptr(Z0), _ptr(Yh), _ptr(Zh),
+                                         _stream(stream)))
+    return Yh, Zh
+
+
+def sample_bases(plan: Plan, S, stream=None):
+    """Per-box Householder Q of the N x c samples in S (S is consumed)."""
+    Q = colmajor_empty(plan.n, S.shape[1], S.device)
+    check(lib().blr_sample_bases(plan._h, S.shape[1], _ptr(S), _ptr(Q), _stream(stream)))
+    return Q
+
+
+def refine_sketch(plan: Plan, op: Operator, U0, V0, gamma_u, gamma_v, stream=None):
+    """Far-field refinement samples SY, SZ (N x r) on the mixed sample bases."""
+    SY = colmajor_empty(plan.n, plan.r, U0.device)
+    SZ = colmajor_empty(plan.n, plan.r, U0.device)
+    check(lib().blr_refine_sketch(plan._h, op._h, U0.shape[1], _ptr(U0), _ptr(V0), _ptr(gamma_u),
+                                  _ptr(gamma_v), _ptr(SY), _ptr(SZ), _stream(stream)))
+    return SY, SZ

@@ -134,6 +134,10 @@ void DeviceTables::release() {
     dfree(colour_ptr);
     dfree(colour_boxes);
     dfree(nf_pair);
+    dfree(Tf);
+    dfree(kstep_ptr);
+    dfree(kstep_box);
+    dfree(nearm);
 }
 
 const DeviceTables& PlanData::tables() {
@@ -161,6 +165,11 @@ const DeviceTables& PlanData::tables() {
         t->colour_ptr = upload(colour_ptr);
         t->colour_boxes = upload(colour_boxes);
         t->nf_pair = upload(nf_pair);
+        std::vector<float> Tf(Trm.begin(), Trm.end());
+        t->Tf = upload(Tf);
+        t->kstep_ptr = upload(kstep_ptr);
+        t->kstep_box = upload(kstep_box);
+        t->nearm = upload(nearm);
     } catch (...) {
         t->release();
         throw;
@@ -180,7 +189,10 @@ PlanData::~PlanData() {
     if (cur >= 0) (void)hipSetDevice(cur);
 }
 
-OpData::~OpData() { dfree(pts); }
+OpData::~OpData() {
+    dfree(pts);
+    dfree(pts32);
+}
 
 UblrData::~UblrData() {
     dfree(U);
@@ -191,6 +203,12 @@ UblrData::~UblrData() {
     dfree(Z);
     dfree(Yhat);
     dfree(Zhat);
+    dfree(Y0);
+    dfree(Z0);
+    dfree(U0);
+    dfree(V0);
+    dfree(SY);
+    dfree(SZ);
 }
 
 }  // namespace blr
@@ -317,6 +335,9 @@ blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const doub
         d->device = current_device();
         d->pts = dalloc_sync(3 * n);
         HIPC(hipMemcpy(d->pts, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<float> soa32(soa.begin(), soa.end());
+        d->pts32 = reinterpret_cast<float*>(dalloc_sync((3 * n + 1) / 2));
+        HIPC(hipMemcpy(d->pts32, soa32.data(), soa32.size() * sizeof(float), hipMemcpyHostToDevice));
         auto* o = new blr_operator;
         o->d = std::move(d);
         *out = o;
@@ -399,6 +420,105 @@ blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const dou
     });
 }
 
+namespace {
+
+bool is_mixed(int precision) {
+    return precision == BLR_PREC_FP32_REFINE || precision == BLR_PREC_BF16_REFINE;
+}
+
+void check_r_lo(const PlanData& P, int r_lo) {
+    if (r_lo < 1 || r_lo > 80) fail(BLR_ERR_UNSUPPORTED, "r_lo must be in 1..80");
+    if (r_lo > P.m_min) fail(BLR_ERR_INVALID_ARG, "r_lo exceeds the smallest box size");
+}
+
+// Packs G (N x r_lo) for the low-precision sketch into a stream-ordered temporary.
+void* pack_lp(AsyncTemps& tmp, const PlanData& P, const DeviceTables& t, int precision, int r_lo,
+              const double* G, hipStream_t s) {
+    const int64_t elems = lp_packed_elems(P, r_lo);
+    const int64_t bytes = elems * (precision == BLR_PREC_BF16_REFINE ? 2 : 4);
+    void* out = tmp.get((bytes + 7) / 8);
+    launch_pack_lp(P, t, precision, r_lo, G, out, s);
+    return out;
+}
+
+// 4 r sum_i m_i (N - sum_{l in N_i} m_l): the far-field products of both sides.
+double refine_flops(const PlanData& P) {
+    double f = 0.0;
+    for (int i = 0; i < P.b; ++i) {
+        double nearcols = 0.0;
+        for (int q = P.near_ptr[i]; q < P.near_ptr[i + 1]; ++q) {
+            const int j = P.near_idx[q];
+            nearcols += static_cast<double>(P.box_ptr[j + 1] - P.box_ptr[j]);
+        }
+        f += static_cast<double>(P.box_ptr[i + 1] - P.box_ptr[i]) * (static_cast<double>(P.n) - nearcols);
+    }
+    return 4.0 * P.r * f;
+}
+
+}  // namespace
+
+blr_status blr_sketch_lowp(const blr_plan* plan, const blr_operator* op, int32_t precision,
+                           int32_t r_lo, const double* G, const double* H, float* Y0, float* Z0,
+                           void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!is_mixed(precision)) fail(BLR_ERR_INVALID_ARG, "precision must be a mixed mode");
+        check_r_lo(P, r_lo);
+        if (!G || !H || !Y0 || !Z0) fail(BLR_ERR_INVALID_ARG, "NULL G, H, Y0 or Z0");
+        const DeviceTables& t = plan->d->tables();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        AsyncTemps tmp(s);
+        void* PG = pack_lp(tmp, P, t, precision, r_lo, G, s);
+        void* PH = pack_lp(tmp, P, t, precision, r_lo, H, s);
+        launch_sketch_lp(o, P, t, precision, r_lo, PG, PH, Y0, Z0, s);
+    });
+}
+
+blr_status blr_tag_postprocess_lowp(const blr_plan* plan, int32_t r_lo, const float* Y0,
+                                    const float* Z0, double* Yhat0, double* Zhat0, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        check_r_lo(P, r_lo);
+        if ((Y0 == nullptr) != (Yhat0 == nullptr) || (Z0 == nullptr) != (Zhat0 == nullptr))
+            fail(BLR_ERR_INVALID_ARG, "input and output of a side must both be given");
+        const DeviceTables& t = plan->d->tables();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (Y0) launch_postprocess_lp(P, t, r_lo, Y0, Yhat0, s);
+        if (Z0) launch_postprocess_lp(P, t, r_lo, Z0, Zhat0, s);
+    });
+}
+
+blr_status blr_sample_bases(const blr_plan* plan, int32_t ncols, double* S, double* Q, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (!S || !Q) fail(BLR_ERR_INVALID_ARG, "NULL S or Q");
+        if (ncols < 1) fail(BLR_ERR_INVALID_ARG, "ncols must be positive");
+        const DeviceTables& t = plan->d->tables();
+        launch_orth_cols(P, t, ncols, ncols, 1, S, nullptr, Q, nullptr, nullptr, nullptr,
+                         static_cast<hipStream_t>(stream));
+    });
+}
+
+blr_status blr_refine_sketch(const blr_plan* plan, const blr_operator* op, int32_t r_lo,
+                             const double* U0, const double* V0, const double* gamma_u,
+                             const double* gamma_v, double* SY, double* SZ, void* stream) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        check_r_lo(P, r_lo);
+        if (!U0 || !V0 || !gamma_u || !gamma_v || !SY || !SZ) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        const DeviceTables& t = plan->d->tables();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        AsyncTemps tmp(s);
+        double* Xv = tmp.get(P.n * P.r);
+        double* Xu = tmp.get(P.n * P.r);
+        launch_mix(P, t, r_lo, V0, gamma_v, Xv, s);
+        launch_mix(P, t, r_lo, U0, gamma_u, Xu, s);
+        launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
+    });
+}
+
 blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
                             const double* H, const blr_compress_opts* opts, void* stream,
                             blr_ublr** out, blr_report* rep) {
@@ -408,75 +528,144 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         const PlanData& P = plan_of(plan);
         const OpData& o = op_of(op, P);
         if (!G || !H) fail(BLR_ERR_INVALID_ARG, "NULL G or H");
-        blr_compress_opts def{BLR_PREC_FP64, 0};
+        blr_compress_opts def{};
+        def.precision = BLR_PREC_FP64;
         const blr_compress_opts& O = opts ? *opts : def;
-        if (O.precision != BLR_PREC_FP64) fail(BLR_ERR_UNSUPPORTED, "unsupported precision");
+        const bool mixed = is_mixed(O.precision);
+        if (!mixed && O.precision != BLR_PREC_FP64) fail(BLR_ERR_UNSUPPORTED, "unsupported precision");
+        if (O.reserved != 0) fail(BLR_ERR_INVALID_ARG, "reserved option field must be 0");
+        const int r_lo = mixed ? (O.r_lo ? O.r_lo : P.r) : P.r;
+        if (mixed) {
+            check_r_lo(P, r_lo);
+            if (!O.gamma_u || !O.gamma_v) fail(BLR_ERR_INVALID_ARG, "mixed modes need gamma_u and gamma_v");
+        }
         hipStream_t s = static_cast<hipStream_t>(stream);
         const DeviceTables& t = plan->d->tables();
-        const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+        const int64_t LR = static_cast<int64_t>(P.ell) * r_lo;
         const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+        const bool keep = O.keep_intermediates != 0;
 
         auto h = std::make_unique<UblrData>();
         h->plan = plan->d;
         h->device = current_device();
+        h->precision = O.precision;
+        h->r_lo = r_lo;
         h->U = dalloc_sync(P.n * P.k);
         h->V = dalloc_sync(P.n * P.k);
         h->Atil = dalloc_sync(bk * bk);
         h->B = dalloc_sync(P.b_values);
         AsyncTemps tmp(s);
-        double *Y, *Z, *Yh, *Zh;
-        if (O.keep_intermediates) {
-            h->Y = Y = dalloc_sync(P.n * LR);
-            h->Z = Z = dalloc_sync(P.n * LR);
-            h->Yhat = dalloc_sync(P.n * P.r);
-            h->Zhat = dalloc_sync(P.n * P.r);
-        } else {
-            Y = tmp.get(P.n * LR);
-            Z = tmp.get(P.n * LR);
-        }
-        Yh = tmp.get(P.n * P.r);
-        Zh = tmp.get(P.n * P.r);
 
-        hipEvent_t ev[6];
+        hipEvent_t ev[8];
         const bool timing = rep != nullptr;
         if (timing)
             for (auto& e : ev) HIPC(hipEventCreate(&e));
         auto mark = [&](int q) {
             if (timing) HIPC(hipEventRecord(ev[q], s));
         };
-        mark(0);
-        launch_sketch(o, P, t, G, H, Y, Z, s);
-        mark(1);
-        launch_postprocess(P, t, Y, Yh, s);
-        launch_postprocess(P, t, Z, Zh, s);
-        if (O.keep_intermediates) {
-            HIPC(hipMemcpyAsync(h->Yhat, Yh, P.n * P.r * sizeof(double), hipMemcpyDeviceToDevice, s));
-            HIPC(hipMemcpyAsync(h->Zhat, Zh, P.n * P.r * sizeof(double), hipMemcpyDeviceToDevice, s));
+        auto keep_copy = [&](double*& dst, const double* src, int64_t count) {
+            dst = dalloc_sync(count);
+            HIPC(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToDevice, s));
+        };
+        // events: 0 start | 1 sketch | 2 post-processing | 3 sample bases + mixing |
+        //         4 refinement | 5 bases | 6 cores | 7 near field
+        if (!mixed) {
+            double *Y, *Z;
+            if (keep) {
+                h->Y = Y = dalloc_sync(P.n * LR);
+                h->Z = Z = dalloc_sync(P.n * LR);
+            } else {
+                Y = tmp.get(P.n * LR);
+                Z = tmp.get(P.n * LR);
+            }
+            double* Yh = tmp.get(P.n * P.r);
+            double* Zh = tmp.get(P.n * P.r);
+            mark(0);
+            launch_sketch(o, P, t, G, H, Y, Z, s);
+            mark(1);
+            launch_postprocess(P, t, Y, Yh, s);
+            launch_postprocess(P, t, Z, Zh, s);
+            if (keep) {
+                keep_copy(h->Yhat, Yh, P.n * P.r);
+                keep_copy(h->Zhat, Zh, P.n * P.r);
+            }
+            mark(2);
+            mark(3);
+            mark(4);
+            launch_orth2(P, t, Yh, Zh, h->U, h->V, nullptr, nullptr, s);
+        } else {
+            const int64_t nf = (P.n * LR + 1) / 2;  // FP32 sketch in doubles
+            float *Y0, *Z0;
+            if (keep) {
+                h->Y0 = Y0 = reinterpret_cast<float*>(dalloc_sync(nf));
+                h->Z0 = Z0 = reinterpret_cast<float*>(dalloc_sync(nf));
+            } else {
+                Y0 = reinterpret_cast<float*>(tmp.get(nf));
+                Z0 = reinterpret_cast<float*>(tmp.get(nf));
+            }
+            double* Yh = tmp.get(P.n * r_lo);
+            double* Zh = tmp.get(P.n * r_lo);
+            double* U0 = tmp.get(P.n * r_lo);
+            double* V0 = tmp.get(P.n * r_lo);
+            double* Xv = tmp.get(P.n * P.r);
+            double* Xu = tmp.get(P.n * P.r);
+            double* SY = tmp.get(P.n * P.r);
+            double* SZ = tmp.get(P.n * P.r);
+            mark(0);
+            void* PG = pack_lp(tmp, P, t, O.precision, r_lo, G, s);
+            void* PH = pack_lp(tmp, P, t, O.precision, r_lo, H, s);
+            launch_sketch_lp(o, P, t, O.precision, r_lo, PG, PH, Y0, Z0, s);
+            mark(1);
+            launch_postprocess_lp(P, t, r_lo, Y0, Yh, s);
+            launch_postprocess_lp(P, t, r_lo, Z0, Zh, s);
+            if (keep) {
+                keep_copy(h->Yhat, Yh, P.n * r_lo);
+                keep_copy(h->Zhat, Zh, P.n * r_lo);
+            }
+            mark(2);
+            launch_orth_cols(P, t, r_lo, r_lo, 1, Yh, Zh, U0, V0, nullptr, nullptr, s);
+            launch_mix(P, t, r_lo, V0, O.gamma_v, Xv, s);
+            launch_mix(P, t, r_lo, U0, O.gamma_u, Xu, s);
+            if (keep) {
+                keep_copy(h->U0, U0, P.n * r_lo);
+                keep_copy(h->V0, V0, P.n * r_lo);
+            }
+            mark(3);
+            launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
+            mark(4);
+            if (keep) {
+                keep_copy(h->SY, SY, P.n * P.r);
+                keep_copy(h->SZ, SZ, P.n * P.r);
+            }
+            launch_orth2(P, t, SY, SZ, h->U, h->V, nullptr, nullptr, s);
         }
-        mark(2);
-        launch_orth2(P, t, Yh, Zh, h->U, h->V, nullptr, nullptr, s);
-        mark(3);
-        launch_cores(o, P, t, h->U, h->V, h->Atil, s);
-        mark(4);
-        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, tmp.get(nearfield_workspace_doubles(P)), s);
         mark(5);
+        launch_cores(o, P, t, h->U, h->V, h->Atil, s);
+        mark(6);
+        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, tmp.get(nearfield_workspace_doubles(P)), s);
+        mark(7);
         if (timing) {
             HIPC(hipStreamSynchronize(s));
-            float ms[5];
-            for (int q = 0; q < 5; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+            float ms[7];
+            for (int q = 0; q < 7; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
             float tot;
-            HIPC(hipEventElapsedTime(&tot, ev[0], ev[5]));
+            HIPC(hipEventElapsedTime(&tot, ev[0], ev[7]));
             for (auto& e : ev) (void)hipEventDestroy(e);
             std::memset(rep, 0, sizeof(*rep));
             rep->ms_sketch = ms[0];
             rep->ms_postprocess = ms[1];
-            rep->ms_orth = ms[2];
-            rep->ms_cores = ms[3];
-            rep->ms_nearfield = ms[4];
+            rep->ms_orth = ms[2] + ms[4];
+            rep->ms_refine = ms[3];
+            rep->ms_cores = ms[5];
+            rep->ms_nearfield = ms[6];
             rep->ms_total = tot;
-            rep->applies_A = LR + bk + static_cast<int64_t>(P.ncol) * P.m_max;
-            rep->applies_At = LR;
+            const int64_t refine_cols = mixed ? static_cast<int64_t>(P.b) * P.r : 0;
+            rep->applies_A = LR + refine_cols + bk + static_cast<int64_t>(P.ncol) * P.m_max;
+            rep->applies_At = LR + refine_cols;
             rep->sketch_flops = 4.0 * static_cast<double>(P.n) * static_cast<double>(P.n) * static_cast<double>(LR);
+            rep->refine_flops = mixed ? refine_flops(P) : 0.0;
+            rep->precision = O.precision;
+            rep->r_lo = mixed ? r_lo : 0;
             std::vector<double> rho = P.rho;
             std::sort(rho.begin(), rho.end());
             rep->rho_min = rho.front();
@@ -491,13 +680,15 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
 
 void blr_ublr_destroy(blr_ublr* h) { delete h; }
 
-blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const double** ptr, int64_t* count) {
+blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count) {
     if (ptr) *ptr = nullptr;
     return guard([&] {
         if (!h || !h->d || !ptr || !count) fail(BLR_ERR_INVALID_ARG, "NULL argument");
         const UblrData& d = *h->d;
         const PlanData& P = *d.plan;
-        const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+        const bool mixed = is_mixed(d.precision);
+        const int rs = mixed ? d.r_lo : P.r;  // sample columns of the sketch
+        const int64_t LR = static_cast<int64_t>(P.ell) * rs;
         const int64_t bk = static_cast<int64_t>(P.b) * P.k;
         switch (part) {
             case BLR_PART_U: *ptr = d.U; *count = P.n * P.k; break;
@@ -506,11 +697,17 @@ blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const double** ptr
             case BLR_PART_B: *ptr = d.B; *count = P.b_values; break;
             case BLR_PART_Y: *ptr = d.Y; *count = P.n * LR; break;
             case BLR_PART_Z: *ptr = d.Z; *count = P.n * LR; break;
-            case BLR_PART_YHAT: *ptr = d.Yhat; *count = P.n * P.r; break;
-            case BLR_PART_ZHAT: *ptr = d.Zhat; *count = P.n * P.r; break;
+            case BLR_PART_YHAT: *ptr = d.Yhat; *count = P.n * rs; break;
+            case BLR_PART_ZHAT: *ptr = d.Zhat; *count = P.n * rs; break;
+            case BLR_PART_Y0: *ptr = d.Y0; *count = P.n * LR; break;
+            case BLR_PART_Z0: *ptr = d.Z0; *count = P.n * LR; break;
+            case BLR_PART_U0: *ptr = d.U0; *count = P.n * rs; break;
+            case BLR_PART_V0: *ptr = d.V0; *count = P.n * rs; break;
+            case BLR_PART_SY: *ptr = d.SY; *count = P.n * P.r; break;
+            case BLR_PART_SZ: *ptr = d.SZ; *count = P.n * P.r; break;
             default: fail(BLR_ERR_INVALID_ARG, "unknown part");
         }
-        if (!*ptr) fail(BLR_ERR_INVALID_ARG, "part not kept (compress with keep_intermediates)");
+        if (!*ptr) fail(BLR_ERR_INVALID_ARG, "part not kept (compress with keep_intermediates, in the mode that has it)");
     });
 }
 

@@ -37,6 +37,10 @@ struct DeviceTables {
     int32_t* colour_ptr = nullptr;   // [ncol+1] CSR of boxes per colour
     int32_t* colour_boxes = nullptr; // [b]
     int32_t* nf_pair = nullptr;      // [b*ncol] near pair index of (i, colour) or -1
+    float* Tf = nullptr;             // [b*ell] row-major T in FP32 (low-precision sketch)
+    int32_t* kstep_ptr = nullptr;    // [b+1] first 32-row source step of each box
+    int32_t* kstep_box = nullptr;    // [nsteps] box of each 32-row source step
+    uint8_t* nearm = nullptr;        // [b*b] 1 if box j is in N_i (i-major)
     void release();
 };
 
@@ -49,6 +53,8 @@ struct PlanData {
     std::vector<int32_t> lattice;
     std::vector<int32_t> near_ptr, near_idx, near_tpos, colour, colour_ptr, colour_boxes, nf_pair, row_box;
     std::vector<int64_t> b_off;
+    std::vector<int32_t> kstep_ptr, kstep_box;  // 32-row source steps per box
+    std::vector<uint8_t> nearm;                 // b x b neighbour mask
     std::vector<double> T;    // column-major b x ell (as supplied)
     std::vector<double> z;    // column-major b x ell
     std::vector<double> rho;  // [b]
@@ -73,6 +79,7 @@ struct OpData {
     const double* A = nullptr;    // dense, borrowed
     int64_t lda = 0;
     double* pts = nullptr;        // kernel: device SoA [3][n] (unused axes zero), owned
+    float* pts32 = nullptr;       // kernel: the same points in FP32, owned
     int device = -1;
     ~OpData();
 };
@@ -88,6 +95,14 @@ struct UblrData {
     double* Z = nullptr;
     double* Yhat = nullptr;
     double* Zhat = nullptr;
+    int precision = BLR_PREC_FP64;
+    int r_lo = 0;                 // sample columns of the low-precision sketch
+    float* Y0 = nullptr;          // mixed modes, keep_intermediates: FP32 sketches
+    float* Z0 = nullptr;
+    double* U0 = nullptr;         // mixed modes, keep_intermediates: sample bases (N x r_lo)
+    double* V0 = nullptr;
+    double* SY = nullptr;         // mixed modes, keep_intermediates: refinement samples (N x r)
+    double* SZ = nullptr;
     ~UblrData();
 };
 

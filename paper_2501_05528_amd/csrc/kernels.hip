@@ -558,9 +558,186 @@ void with_source(const OpData& op, int trans, F&& f) {
     }
 }
 
+// ------------------------------------------------------------ refinement sketch
+// Far-field samples of the mixed-precision mode (one FP64 sketch on the
+// mixed sample bases):
+//   S0(I_i, :) = sum_{l in F_i} A(I_i, I_l) X0(I_l, :)   and S1 from X1,
+// with the same kernel tile for both sides when the matrix is symmetric.  Near
+// blocks are masked to zero as the tile is generated; a source box that is
+// near to every row of the workgroup is skipped.  Workgroup: 64 target rows;
+// wave w owns rows 16w..16w+15 (four 4-row tiles of v_mfma_f64_4x4x4f64, the
+// layout of k_sketch) and every column tile of both sides.
+template <class AS, int NTR, int NSIDE>
+__global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restrict__ box_ptr,
+                                                   const int32_t* __restrict__ row_box,
+                                                   const uint8_t* __restrict__ nearm, int nbox,
+                                                   const double* __restrict__ X0,
+                                                   const double* __restrict__ X1, int64_t n, int r,
+                                                   double* __restrict__ S0, double* __restrict__ S1) {
+    constexpr int BM = 64, MA = 4, KT = 16, CW = NTR * 16, BW = NSIDE * CW;
+    constexpr int BPT = (KT * BW + 255) / 256;
+    __shared__ double sA[2][KT * BM];
+    __shared__ double sB[2][KT * BW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
+    const int64_t rlast = min(row0 + BM, n) - 1;
+    const int box_first = row_box[row0], box_last = row_box[rlast];
+    const bool single = box_first == box_last;
+    // generation: thread owns row tid % 64 and sources tid / 64 + 4u, u < 4
+    const int arow = tid & 63, akk = tid >> 6;
+    const int64_t gi = min(row0 + arow, n - 1);
+    const auto rp = A.row(gi);
+    const int64_t mybox_row = static_cast<int64_t>(row_box[gi]) * nbox;
+    const double* gptr[BPT];
+    bool gcol[BPT], gin[BPT];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int e = tid + 256 * u;
+        const int cc = e % BW;
+        const int side = cc / CW, c = cc % CW;
+        gin[u] = e < KT * BW;
+        gcol[u] = gin[u] && c < r;
+        gptr[u] = (side ? X1 : X0) + static_cast<int64_t>(gcol[u] ? c : 0) * n;
+    }
+    double gv[BPT];
+    auto fetch_b = [&](int64_t jb, int64_t jend) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int kk = (tid + 256 * u) / BW;
+            gv[u] = gptr[u][min(jb + kk, jend - 1)];
+        }
+    };
+    auto store_b = [&](int buf, int64_t jb, int64_t jend) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int e = tid + 256 * u;
+            const int kk = e / BW;
+            if (gin[u]) sB[buf][e] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+        }
+    };
+    auto gen_a = [&](int buf, int l, int64_t jb, int64_t jend) {
+        const bool far = nearm[mybox_row + l] == 0;
+#pragma unroll
+        for (int u = 0; u < KT / 4; ++u) {
+            const int kk = akk + 4 * u;
+            const int64_t j = jb + kk;
+            const double v = A.val(rp, A.col(j < jend ? j : jend - 1));
+            sA[buf][kk * BM + arow] = (far && j < jend) ? v : 0.0;
+        }
+    };
+    // next source box at or after l that is not near to the whole workgroup
+    auto next_box = [&](int l) {
+        while (l < nbox && single && nearm[static_cast<int64_t>(box_first) * nbox + l]) ++l;
+        return l;
+    };
+
+    double acc[NSIDE][MA][NTR];
+#pragma unroll
+    for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+        for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+            for (int nt = 0; nt < NTR; ++nt) acc[sd][ma][nt] = 0.0;
+
+    int l = next_box(0);
+    if (l < nbox) {
+        int64_t j0 = box_ptr[l], jend = box_ptr[l + 1];
+        fetch_b(j0, jend);
+        store_b(0, j0, jend);
+        gen_a(0, l, j0, jend);
+        __syncthreads();
+        int buf = 0;
+        for (;;) {
+            int ln = l;
+            int64_t jn = j0 + KT, jendn = jend;
+            if (jn >= jend) {
+                ln = next_box(l + 1);
+                if (ln < nbox) {
+                    jn = box_ptr[ln];
+                    jendn = box_ptr[ln + 1];
+                }
+            }
+            const bool more = ln < nbox;
+            if (more) fetch_b(jn, jendn);
+#pragma unroll
+            for (int ks = 0; ks < KT / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                double a[MA];
+#pragma unroll
+                for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + wave * 16 + ma * 4 + (lane & 3)];
+                double bb[NSIDE][NTR];
+#pragma unroll
+                for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                    for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][kr * BW + sd * CW + nt * 16 + (lane & 15)];
+#pragma unroll
+                for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                    for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+                        for (int nt = 0; nt < NTR; ++nt) acc[sd][ma][nt] = mfma44(a[ma], bb[sd][nt], acc[sd][ma][nt]);
+            }
+            if (!more) break;
+            store_b(buf ^ 1, jn, jendn);
+            gen_a(buf ^ 1, ln, jn, jendn);
+            __syncthreads();
+            buf ^= 1;
+            l = ln;
+            j0 = jn;
+            jend = jendn;
+        }
+    }
+#pragma unroll
+    for (int sd = 0; sd < NSIDE; ++sd) {
+        double* So = sd ? S1 : S0;
+#pragma unroll
+        for (int ma = 0; ma < MA; ++ma) {
+            const int64_t row = row0 + wave * 16 + ma * 4 + (lane >> 4);
+#pragma unroll
+            for (int nt = 0; nt < NTR; ++nt) {
+                const int c = nt * 16 + (lane & 15);
+                if (row < n && c < r) So[row + static_cast<int64_t>(c) * n] = acc[sd][ma][nt];
+            }
+        }
+    }
+}
+
+template <class AS>
+void refine_launch(AS A, const PlanData& P, const DeviceTables& t, const double* X0,
+                   const double* X1, int nside, double* S0, double* S1, hipStream_t s) {
+    const int ntr = (P.r + 15) / 16;
+    const dim3 grid(static_cast<unsigned>((P.n + 63) / 64));
+#define BLR_REFINE_CASE(NTRV, NSV)                                                                \
+    hipLaunchKernelGGL((k_refine<AS, NTRV, NSV>), grid, dim3(256), 0, s, A, t.box_ptr, t.row_box, \
+                       t.nearm, P.b, X0, X1, P.n, P.r, S0, S1)
+    if (nside == 2) {
+        switch (ntr) {
+            case 1: BLR_REFINE_CASE(1, 2); break;
+            case 2: BLR_REFINE_CASE(2, 2); break;
+            case 3: BLR_REFINE_CASE(3, 2); break;
+            case 4: BLR_REFINE_CASE(4, 2); break;
+            case 5: BLR_REFINE_CASE(5, 2); break;
+            default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the refinement sketch");
+        }
+    } else {
+        switch (ntr) {
+            case 1: BLR_REFINE_CASE(1, 1); break;
+            case 2: BLR_REFINE_CASE(2, 1); break;
+            case 3: BLR_REFINE_CASE(3, 1); break;
+            case 4: BLR_REFINE_CASE(4, 1); break;
+            case 5: BLR_REFINE_CASE(5, 1); break;
+            default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the refinement sketch");
+        }
+    }
+#undef BLR_REFINE_CASE
+    check_launch("refinement sketch");
+}
+
 // ------------------------------------------------------------ post-processing
 // Yhat(row, c) = sum_s z(box(row), s) * Y(row, s*r + c)   (Alg. 2 weighted sum)
-__global__ __launch_bounds__(256) void k_postprocess(const double* __restrict__ Y,
+template <class TIN>
+__global__ __launch_bounds__(256) void k_postprocess(const TIN* __restrict__ Y,
                                                      double* __restrict__ Yh,
                                                      const double* __restrict__ z,
                                                      const int32_t* __restrict__ rb, int64_t n,
@@ -571,7 +748,7 @@ __global__ __launch_bounds__(256) void k_postprocess(const double* __restrict__ 
     const int64_t row = idx - static_cast<int64_t>(c) * n;
     const double* zb = z + static_cast<int64_t>(rb[row]) * ell;
     double acc = 0.0;
-    for (int s = 0; s < ell; ++s) acc += zb[s] * Y[row + static_cast<int64_t>(s * r + c) * n];
+    for (int s = 0; s < ell; ++s) acc += zb[s] * static_cast<double>(Y[row + static_cast<int64_t>(s * r + c) * n]);
     Yh[row + static_cast<int64_t>(c) * n] = acc;
 }
 
@@ -595,7 +772,7 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
                                               const int64_t* box_ptr, int nbox, int r, int k,
                                               double* Q0, double* Q1, int64_t ldQ,
                                               double* sigma0, double* sigma1, int m_in_lds,
-                                              int max_sweeps) {
+                                              int max_sweeps, int qr_only) {
     extern __shared__ double smem[];
     __shared__ double rdiag[128], vvs[128], norms[128];
     __shared__ int order[128];
@@ -663,9 +840,10 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     }
     __syncthreads();
     // 2. one-sided Jacobi on the columns of Rt, rotations accumulated in J
+    // (skipped in QR-only mode: then U = the first k columns of Q)
     const double tol = sqrt(static_cast<double>(r)) * 2.220446049250313e-16;
     const int nr = r + (r & 1);
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int sweep = 0; sweep < (qr_only ? 0 : max_sweeps); ++sweep) {
         if (tid == 0) changed = 0;
         __syncthreads();
         for (int round = 0; round < nr - 1; ++round) {
@@ -724,7 +902,7 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
         const double nv = norms[tid];
         int rank = 0;
         for (int c = 0; c < r; ++c) rank += (norms[c] > nv) || (norms[c] == nv && c < tid);
-        order[rank] = tid;
+        order[qr_only ? tid : rank] = tid;
     }
     __syncthreads();
     if (sigma && tid < r) sigma[static_cast<int64_t>(box) * r + tid] = norms[order[tid]];
@@ -1329,6 +1507,16 @@ void launch_sketch(const OpData& op, const PlanData& P, const DeviceTables& t, c
     }
 }
 
+void launch_refine(const OpData& op, const PlanData& P, const DeviceTables& t, const double* X0,
+                   const double* X1, double* S0, double* S1, hipStream_t s) {
+    if (op.type == OpType::Kernel) {
+        with_source(op, 0, [&](auto A) { refine_launch(A, P, t, X0, X1, 2, S0, S1, s); });
+    } else {
+        with_source(op, 0, [&](auto A) { refine_launch(A, P, t, X0, X0, 1, S0, S0, s); });
+        with_source(op, 1, [&](auto A) { refine_launch(A, P, t, X1, X1, 1, S1, S1, s); });
+    }
+}
+
 void launch_op_apply(const OpData& op, int trans, int64_t ncols, const double* X, int64_t ldx,
                      double* Y, int64_t ldy, hipStream_t s) {
     if (ncols > (1 << 30)) fail(BLR_ERR_INVALID_ARG, "too many columns");
@@ -1340,16 +1528,32 @@ void launch_op_apply(const OpData& op, int trans, int64_t ncols, const double* X
 void launch_postprocess(const PlanData& P, const DeviceTables& t, const double* Y, double* Yhat,
                         hipStream_t s) {
     const int64_t total = P.n * P.r;
-    hipLaunchKernelGGL(k_postprocess, dim3((total + 255) / 256), dim3(256), 0, s, Y, Yhat, t.z,
+    hipLaunchKernelGGL(k_postprocess<double>, dim3((total + 255) / 256), dim3(256), 0, s, Y, Yhat, t.z,
                        t.row_box, P.n, P.r, P.ell);
     check_launch("tag post-processing");
 }
 
+void launch_postprocess_lp(const PlanData& P, const DeviceTables& t, int r_lo, const float* Y,
+                           double* Yhat, hipStream_t s) {
+    const int64_t total = P.n * r_lo;
+    hipLaunchKernelGGL(k_postprocess<float>, dim3((total + 255) / 256), dim3(256), 0, s, Y, Yhat, t.z,
+                       t.row_box, P.n, r_lo, P.ell);
+    check_launch("tag post-processing of the low-precision sketch");
+}
+
 void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* S1, double* Q0,
                   double* Q1, double* sig0, double* sig1, hipStream_t s) {
-    if (P.r > 128) fail(BLR_ERR_UNSUPPORTED, "k + p > 128 is not supported by the basis kernel");
-    const size_t small = static_cast<size_t>(2) * P.r * P.r * sizeof(double);
-    const size_t big = static_cast<size_t>(P.m_max) * P.r * sizeof(double);
+    launch_orth_cols(P, t, P.r, P.k, 0, S0, S1, Q0, Q1, sig0, sig1, s);
+}
+
+void launch_orth_cols(const PlanData& P, const DeviceTables& t, int r, int k, int qr_only,
+                      double* S0, double* S1, double* Q0, double* Q1, double* sig0, double* sig1,
+                      hipStream_t s) {
+    if (r > 128) fail(BLR_ERR_UNSUPPORTED, "more than 128 sample columns are not supported by the basis kernel");
+    if (r > P.m_min) fail(BLR_ERR_UNSUPPORTED, "sample columns exceed the smallest box size");
+    if (k > r) fail(BLR_ERR_INVALID_ARG, "more basis columns than sample columns");
+    const size_t small = static_cast<size_t>(2) * r * r * sizeof(double);
+    const size_t big = static_cast<size_t>(P.m_max) * r * sizeof(double);
     const size_t lds_limit = 160 * 1024 - 4096;  // gfx950: 160 KiB per workgroup, minus statics
     if (small > lds_limit) fail(BLR_ERR_UNSUPPORTED, "k + p too large for the basis kernel");
     const int m_in_lds = (small + big <= lds_limit) ? 1 : 0;
@@ -1361,7 +1565,7 @@ void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* 
     }
     const int nsides = S1 ? 2 : 1;
     hipLaunchKernelGGL(k_orth, dim3(nsides * P.b), dim3(256), dyn, s, S0, S1 ? S1 : S0, P.n, t.box_ptr,
-                       P.b, P.r, P.k, Q0, Q1 ? Q1 : Q0, P.n, sig0, sig1, m_in_lds, 60);
+                       P.b, r, k, Q0, Q1 ? Q1 : Q0, P.n, sig0, sig1, m_in_lds, 60, qr_only);
     check_launch("orthonormalisation");
 }
 

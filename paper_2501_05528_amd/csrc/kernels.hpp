@@ -23,12 +23,34 @@ void launch_postprocess(const PlanData& P, const DeviceTables& t, const double* 
 
 void launch_orth(const PlanData& P, const DeviceTables& t, double* S, double* Q, double* sigma,
                  hipStream_t s);
+// General form: S has r columns, Q receives k <= r; qr_only = 1 gives the first k
+// columns of the Householder Q (sign rule applied) without the SVD step.
+void launch_orth_cols(const PlanData& P, const DeviceTables& t, int r, int k, int qr_only,
+                      double* S0, double* S1, double* Q0, double* Q1, double* sig0, double* sig1,
+                      hipStream_t s);
 // Both sides in one launch (S1/Q1 may be null for one side).
 void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* S1, double* Q0,
                   double* Q1, double* sig0, double* sig1, hipStream_t s);
 
 void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
                   const double* V, double* Atil, hipStream_t s);
+
+// Mixed-precision mode (kernels_lp.hip): [G|H] packed per side into MFMA
+// fragment order (lp_packed_elems elements of 2 bytes for BF16, 4 for FP32),
+// the low-precision tagged sketch into FP32 Y, Z (N x ell r_lo), and the mixing
+// X(I_l) = Q0(I_l) gamma[l] (gamma C-ordered b x r_lo x r).
+int64_t lp_packed_elems(const PlanData& P, int r_lo);
+void launch_pack_lp(const PlanData& P, const DeviceTables& t, int precision, int r_lo,
+                    const double* G, void* out, hipStream_t s);
+void launch_sketch_lp(const OpData& op, const PlanData& P, const DeviceTables& t, int precision,
+                      int r_lo, const void* PG, const void* PH, float* Y, float* Z, hipStream_t s);
+void launch_postprocess_lp(const PlanData& P, const DeviceTables& t, int r_lo, const float* Y,
+                           double* Yhat, hipStream_t s);
+void launch_mix(const PlanData& P, const DeviceTables& t, int r_lo, const double* Q0,
+                const double* gamma, double* X, hipStream_t s);
+// FP64 far-field refinement sketch: S0 = far(A) X0, S1 = far(A*) X1 (N x r each).
+void launch_refine(const OpData& op, const PlanData& P, const DeviceTables& t, const double* X0,
+                   const double* X1, double* S0, double* S1, hipStream_t s);
 
 // Near field; work must hold nearfield_workspace_doubles(P) doubles.
 int64_t nearfield_workspace_doubles(const PlanData& P);

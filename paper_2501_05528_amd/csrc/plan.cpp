@@ -17,6 +17,7 @@
 //   entry positive.
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <set>
@@ -464,6 +465,21 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
     P->row_box.resize(P->n);
     for (int i = 0; i < b; ++i)
         for (int64_t a = P->box_ptr[i]; a < P->box_ptr[i + 1]; ++a) P->row_box[a] = i;
+    // 32-row source steps of the low-precision sketch (steps never straddle a box)
+    P->kstep_ptr.assign(b + 1, 0);
+    for (int i = 0; i < b; ++i) {
+        const int64_t steps = (P->box_ptr[i + 1] - P->box_ptr[i] + 31) / 32;
+        if (P->kstep_ptr[i] + steps > INT32_MAX) fail(BLR_ERR_UNSUPPORTED, "too many source steps");
+        P->kstep_ptr[i + 1] = P->kstep_ptr[i] + static_cast<int32_t>(steps);
+    }
+    P->kstep_box.resize(P->kstep_ptr[b]);
+    for (int i = 0; i < b; ++i)
+        for (int q = P->kstep_ptr[i]; q < P->kstep_ptr[i + 1]; ++q) P->kstep_box[q] = i;
+    // neighbour mask for the far-field refinement sketch
+    P->nearm.assign(static_cast<size_t>(b) * b, 0);
+    for (int i = 0; i < b; ++i)
+        for (int q = P->near_ptr[i]; q < P->near_ptr[i + 1]; ++q)
+            P->nearm[static_cast<size_t>(i) * b + P->near_idx[q]] = 1;
     // tagging matrix and tag vectors
     P->T.assign(prm->T, prm->T + static_cast<size_t>(b) * P->ell);
     for (double v : P->T)
