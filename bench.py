@@ -28,6 +28,7 @@ import workloads as W  # noqa: E402
 
 METRIC = "BLR compressions/s + operator-applies per compression at 1e-8 rel err; %MFMA/HBM"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_laplace2d_n65536_fp64.md")
@@ -72,8 +73,43 @@ def setup(wl_name):
     plan_s = time.perf_counter() - t0
     op = P.Operator.kernel(wl.kind, g.pts)
     Gd, Hd = P.colmajor(G), P.colmajor(H)
+    # mixed modes: r_lo = r (p_lo = p) and the refinement's mixing blocks
+    gu, gv = W.refinement_gammas(wl.seed, g.nboxes, wl.r, wl.r)
+    gud = torch.as_tensor(gu, device="cuda")
+    gvd = torch.as_tensor(gv, device="cuda")
     torch.cuda.synchronize()
-    return dict(wl=wl, g=g, T=T, G=G, H=H, plan=plan, op=op, Gd=Gd, Hd=Hd, plan_s=plan_s, P=P)
+    return dict(wl=wl, g=g, T=T, G=G, H=H, plan=plan, op=op, Gd=Gd, Hd=Hd, gud=gud, gvd=gvd,
+                plan_s=plan_s, P=P)
+
+
+def run_mode(S, precision, steps, warmup, with_error):
+    """Times `steps` compressions in one precision mode; returns rate, stage times,
+    report of the first timed step and the last handle's error."""
+    import torch
+    P, plan, op = S["P"], S["plan"], S["op"]
+    kw = {} if precision == "fp64" else dict(precision=precision, gamma_u=S["gud"], gamma_v=S["gvd"])
+    for w in range(warmup):
+        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True, **kw)
+        log(f"{precision} warmup {w}: {rep['ms_total']:.1f} ms (sketch {rep['ms_sketch']:.1f})")
+        del h
+    torch.cuda.synchronize()
+    handles, reps = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True, **kw)
+        handles.append(h)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"{precision}: timed {steps} steps in {elapsed:.3f} s")
+    err = None
+    if with_error:
+        err = handles[-1].error_fro(op)
+        log(f"{precision}: relative Frobenius error {err:.3e}")
+    del handles
+    stage = {k: float(np.mean([r[k] for r in reps])) for k in
+             ("ms_sketch", "ms_postprocess", "ms_orth", "ms_refine", "ms_cores", "ms_nearfield", "ms_total")}
+    return dict(value=steps / elapsed, ms_step=1000.0 * elapsed / steps, stage=stage, rep=reps[0], err=err)
 
 
 def cpu_baseline(S, nsample_boxes=4):
@@ -145,6 +181,8 @@ def main():
     ap.add_argument("--workload", default="laplace2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision (BF16 / FP32 sketch + FP64 refinement) runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(a plain kernel of known traffic for scaling rocprofv3 byte counters)")
@@ -156,22 +194,9 @@ def main():
     import torch
     log(f"setup {args.workload}")
     S = setup(args.workload)
-    P, plan, op = S["P"], S["plan"], S["op"]
+    plan = S["plan"]
     wl, g = S["wl"], S["g"]
-    for w in range(args.warmup):
-        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True)
-        log(f"warmup {w}: {rep['ms_total']:.1f} ms (sketch {rep['ms_sketch']:.1f})")
-        del h
-    torch.cuda.synchronize()
-    handles, reps = [], []
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        h, rep = P.compress(plan, op, S["Gd"], S["Hd"], report=True)
-        handles.append(h)
-        reps.append(rep)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    res = run_mode(S, "fp64", args.steps, args.warmup, not args.no_error)
     if args.calib_copy_mib:
         nel = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -180,27 +205,20 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
         del src, dst
-    last = handles[-1]
-    err_fro = None
-    if not args.no_error:
-        err_fro = last.error_fro(op)
-        log(f"relative Frobenius error {err_fro:.3e}")
-    del handles
-    ms_step = 1000.0 * elapsed / args.steps
-    value = args.steps / elapsed
-    stage = {k: float(np.mean([r[k] for r in reps])) for k in
-             ("ms_sketch", "ms_postprocess", "ms_orth", "ms_cores", "ms_nearfield", "ms_total")}
-    applies = int(reps[0]["applies_A"] + reps[0]["applies_At"])
-    sketch_flops = reps[0]["sketch_flops"]
+    value = res["value"]
+    stage = res["stage"]
+    rep0 = res["rep"]
+    applies = int(rep0["applies_A"] + rep0["applies_At"])
+    sketch_flops = rep0["sketch_flops"]
     achieved = sketch_flops / (stage["ms_sketch"] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "k_opgemm (tagged sketch, FP64 MFMA)",
+    roofline = {"bound": "mfma", "kernel": "k_sketch (tagged sketch, FP64 MFMA)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": measured_sketch_traffic(wl.name),
                 "algorithmic_flops_per_launch": sketch_flops}
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "compressions/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["ms_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "kernel": wl.kind, "N": g.n, "boxes": g.nboxes,
@@ -208,11 +226,35 @@ def main():
                    "precision": "fp64"},
         "applies_per_compression": applies,
         "applies_per_s": round(applies * value, 1),
-        "rel_err_fro": err_fro,
-        "stage_ms": {k: round(v, 3) for k, v in stage.items()},
+        "rel_err_fro": res["err"],
+        "stage_ms": {k: round(v, 3) for k, v in stage.items() if k != "ms_refine"},
         "plan_s": round(S["plan_s"], 3),
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        mixed = {}
+        for prec in ("bf16", "fp32"):
+            m = run_mode(S, prec, args.steps, args.warmup, not args.no_error)
+            rp = m["rep"]
+            st = m["stage"]
+            sk = rp["sketch_flops"] / (st["ms_sketch"] * 1e-3) / 1e12
+            rf = rp["refine_flops"] / (st["ms_refine"] * 1e-3) / 1e12
+            mixed[prec] = {
+                "value": round(m["value"], 4), "unit": "compressions/s",
+                "ms_per_step": round(m["ms_step"], 3),
+                "speedup_vs_fp64": round(m["value"] / value, 3),
+                "rel_err_fro": m["err"],
+                "r_lo": rp["r_lo"],
+                "applies_per_compression": int(rp["applies_A"] + rp["applies_At"]),
+                "stage_ms": {k: round(v, 3) for k, v in st.items()},
+                "sketch_roofline": {"bound": "mfma", "achieved": round(sk, 2), "peak": PEAK_TFLOPS[prec],
+                                    "unit": "TFLOP/s", "frac": round(sk / PEAK_TFLOPS[prec], 4),
+                                    "algorithmic_flops_per_launch": rp["sketch_flops"]},
+                "refine_roofline": {"bound": "mfma", "achieved": round(rf, 2), "peak": PEAK_FP64_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(rf / PEAK_FP64_TFLOPS, 4),
+                                    "algorithmic_flops_per_launch": rp["refine_flops"]},
+            }
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(S)
