@@ -123,6 +123,11 @@ struct KernelSrc {
         c[2] = pz[j];
     }
     __device__ P col_staged(const double* c, int64_t j) const { return P{c[0], c[1], c[2], j}; }
+    // split entry evaluation: pre() issues the loads of column j, fin() the arithmetic,
+    // so a kernel can load the next step's columns before computing on the current one
+    using Pre = P;
+    __device__ Pre pre(const P&, int64_t j) const { return col(j); }
+    __device__ double fin(const P& a, const Pre& b) const { return val(a, b); }
 };
 
 struct DenseSrc {  // A(i, j) = A[i + j*lda]
@@ -137,6 +142,9 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
     static constexpr int STAGE = 1;
     __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
     __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
+    using Pre = double;
+    __device__ Pre pre(const P& a, int64_t j) const { return A[a.i + j * lda]; }
+    __device__ double fin(const P&, Pre v) const { return v; }
 };
 
 struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
@@ -151,6 +159,9 @@ struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
     static constexpr int STAGE = 1;
     __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
     __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
+    using Pre = double;
+    __device__ Pre pre(const P& a, int64_t j) const { return A[j + a.i * lda]; }
+    __device__ double fin(const P&, Pre v) const { return v; }
 };
 
 // ------------------------------------------------------------ B operands
@@ -366,7 +377,8 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     constexpr int AGEN = BM * KT;                                // A tile entries per step
     static_assert(AGEN <= 256, "tile shape");
     __shared__ double sA[2][KT * BM];
-    __shared__ double sB[2][KT * BW];
+    constexpr int KTP = KT + 1;                  // padded column stride of the B tile
+    __shared__ double sB[2][KTP * BW];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
@@ -380,13 +392,15 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     const int arow = tid % BM, akk = tid / BM;
     const int64_t gi = row0 + arow;
     const auto rp = A.row(gi < n ? gi : n - 1);
-    // B tile: element e = tid + 256*u -> row e / BW, column e % BW (side = col / CW)
+    // B tile: element e = tid + 256*u -> row e % KT, column e / KT (side = column / CW), so
+    // KT consecutive threads read one column's KT consecutive rows; LDS holds the tile
+    // column-major with stride KTP
     const double* gptr[BPT];
     bool gcol[BPT], gin[BPT];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
         const int e = tid + 256 * u;
-        const int cc = e % BW;
+        const int cc = e / KT;                   // tile column (coalesced: KT rows per column)
         const int side = cc / CW, c = cc % CW;
         gin[u] = e < KT * BW;
         gcol[u] = gin[u] && c < r;
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     auto fetch_b = [&](int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
-            const int kk = (tid + 256 * u) / BW;
+            const int kk = (tid + 256 * u) % KT;
             gv[u] = gptr[u][min(jb + kk, jend - 1)];
         }
     };
@@ -404,12 +418,18 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             const int e = tid + 256 * u;
-            const int kk = e / BW;
-            if (gin[u]) sB[buf][e] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+            const int kk = e % KT, cc = e / KT;
+            if (gin[u]) sB[buf][cc * KTP + kk] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
         }
     };
-    auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
-        if (agen) sA[buf][akk * BM + arow] = A.val(rp, A.col(min(jb + akk, jend - 1)));
+    // the next step's kernel column is loaded before the current step's MFMAs
+    // (pre_a) and turned into an entry after them (gen_a)
+    typename AS::Pre apre;
+    auto pre_a = [&](int64_t jb, int64_t jend) {
+        if (agen) apre = A.pre(rp, min(jb + akk, jend - 1));
+    };
+    auto gen_a = [&](int buf) {
+        if (agen) sA[buf][akk * BM + arow] = A.fin(rp, apre);
     };
 
     double acc[SVW][NSIDE][MA][NTR];
@@ -424,15 +444,19 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
 
     int l = 0;
     int64_t j0 = box_ptr[0], jend = box_ptr[1];
+    double tw[SVW], twn[SVW];
+    auto load_tw = [&](double* w, int lb) {
+#pragma unroll
+        for (int v = 0; v < SVW; ++v) w[v] = T[static_cast<int64_t>(lb) * ell + min(s_lo + v, ell - 1)];
+    };
     fetch_b(j0, jend);
+    pre_a(j0, jend);
+    load_tw(tw, 0);
     store_b(0, j0, jend);
-    gen_a(0, j0, jend);
+    gen_a(0);
     __syncthreads();
     int buf = 0;
     for (;;) {
-        double tw[SVW];
-#pragma unroll
-        for (int v = 0; v < SVW; ++v) tw[v] = T[static_cast<int64_t>(l) * ell + min(s_lo + v, ell - 1)];
         int ln = l;
         int64_t jn = j0 + KT, jendn = jend;
         if (jn >= jend) {
@@ -443,7 +467,11 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
             }
         }
         const bool more = ln < nbox;
-        if (more) fetch_b(jn, jendn);
+        if (more) {
+            fetch_b(jn, jendn);
+            pre_a(jn, jendn);
+            load_tw(twn, ln);
+        }
 #pragma unroll
         for (int ks = 0; ks < KT / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -454,7 +482,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
 #pragma unroll
             for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
-                for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][kr * BW + sd * CW + nt * 16 + (lane & 15)];
+                for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][(sd * CW + nt * 16 + (lane & 15)) * KTP + kr];
 #pragma unroll
             for (int v = 0; v < SVW; ++v) {
                 if (v < nsv) {
@@ -473,12 +501,14 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
         }
         if (!more) break;
         store_b(buf ^ 1, jn, jendn);
-        gen_a(buf ^ 1, jn, jendn);
+        gen_a(buf ^ 1);
         __syncthreads();
         buf ^= 1;
         l = ln;
         j0 = jn;
         jend = jendn;
+#pragma unroll
+        for (int v = 0; v < SVW; ++v) tw[v] = twn[v];
     }
     // epilogue: (s, side) column c -> Y_side(:, s*r + c)
 #pragma unroll
@@ -577,7 +607,8 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     constexpr int BM = 64, MA = 4, KT = 16, CW = NTR * 16, BW = NSIDE * CW;
     constexpr int BPT = (KT * BW + 255) / 256;
     __shared__ double sA[2][KT * BM];
-    __shared__ double sB[2][KT * BW];
+    constexpr int KTP = KT + 1;                  // padded column stride of the B tile
+    __shared__ double sB[2][KTP * BW];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
@@ -589,12 +620,14 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     const int64_t gi = min(row0 + arow, n - 1);
     const auto rp = A.row(gi);
     const int64_t mybox_row = static_cast<int64_t>(row_box[gi]) * nbox;
+    // B tile [X0 | X1]: element e = tid + 256*u -> row e % KT, column e / KT (coalesced
+    // column reads), stored column-major in LDS with stride KTP
     const double* gptr[BPT];
     bool gcol[BPT], gin[BPT];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
         const int e = tid + 256 * u;
-        const int cc = e % BW;
+        const int cc = e / KT;                   // tile column (coalesced: KT rows per column)
         const int side = cc / CW, c = cc % CW;
         gin[u] = e < KT * BW;
         gcol[u] = gin[u] && c < r;
@@ -604,7 +637,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     auto fetch_b = [&](int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
-            const int kk = (tid + 256 * u) / BW;
+            const int kk = (tid + 256 * u) % KT;
             gv[u] = gptr[u][min(jb + kk, jend - 1)];
         }
     };
@@ -612,18 +645,28 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             const int e = tid + 256 * u;
-            const int kk = e / BW;
-            if (gin[u]) sB[buf][e] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+            const int kk = e % KT, cc = e / KT;
+            if (gin[u]) sB[buf][cc * KTP + kk] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
         }
     };
-    auto gen_a = [&](int buf, int l, int64_t jb, int64_t jend) {
-        const bool far = nearm[mybox_row + l] == 0;
+    // the next step's kernel columns and far mask are loaded before the current
+    // step's MFMAs (pre_a) and turned into entries after them (gen_a)
+    typename AS::Pre apre[KT / 4];
+    bool far_pre = true;
+    auto pre_a = [&](int l, int64_t jb, int64_t jend) {
+        far_pre = nearm[mybox_row + l] == 0;
+#pragma unroll
+        for (int u = 0; u < KT / 4; ++u) {
+            const int64_t j = jb + akk + 4 * u;
+            apre[u] = A.pre(rp, j < jend ? j : jend - 1);
+        }
+    };
+    auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < KT / 4; ++u) {
             const int kk = akk + 4 * u;
-            const int64_t j = jb + kk;
-            const double v = A.val(rp, A.col(j < jend ? j : jend - 1));
-            sA[buf][kk * BM + arow] = (far && j < jend) ? v : 0.0;
+            const double v = A.fin(rp, apre[u]);
+            sA[buf][kk * BM + arow] = (far_pre && jb + kk < jend) ? v : 0.0;
         }
     };
     // next source box at or after l that is not near to the whole workgroup
@@ -644,8 +687,9 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     if (l < nbox) {
         int64_t j0 = box_ptr[l], jend = box_ptr[l + 1];
         fetch_b(j0, jend);
+        pre_a(l, j0, jend);
         store_b(0, j0, jend);
-        gen_a(0, l, j0, jend);
+        gen_a(0, j0, jend);
         __syncthreads();
         int buf = 0;
         for (;;) {
@@ -659,7 +703,10 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
                 }
             }
             const bool more = ln < nbox;
-            if (more) fetch_b(jn, jendn);
+            if (more) {
+                fetch_b(jn, jendn);
+                pre_a(ln, jn, jendn);
+            }
 #pragma unroll
             for (int ks = 0; ks < KT / 4; ++ks) {
                 const int kr = ks * 4 + (lane >> 4);
@@ -670,7 +717,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
 #pragma unroll
                 for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
-                    for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][kr * BW + sd * CW + nt * 16 + (lane & 15)];
+                    for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][(sd * CW + nt * 16 + (lane & 15)) * KTP + kr];
 #pragma unroll
                 for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
@@ -680,7 +727,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
             }
             if (!more) break;
             store_b(buf ^ 1, jn, jendn);
-            gen_a(buf ^ 1, ln, jn, jendn);
+            gen_a(buf ^ 1, jn, jendn);
             __syncthreads();
             buf ^= 1;
             l = ln;

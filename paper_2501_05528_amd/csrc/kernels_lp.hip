@@ -59,6 +59,10 @@ struct KernelSrc32 {
         const float v = kval32<KIND>(dx * dx + dy * dy + dz * dz);
         return a.i == b.i ? diag : v;
     }
+    // split entry evaluation (loads of column j, then the arithmetic)
+    using Pre = P;
+    __device__ Pre pre(const P&, int64_t j) const { return col(j); }
+    __device__ float fin(const P& a, const Pre& b) const { return val(a, b); }
 };
 
 struct DenseSrc32 {  // A(i, j) = A[i + j*lda], rounded to FP32
@@ -70,6 +74,9 @@ struct DenseSrc32 {  // A(i, j) = A[i + j*lda], rounded to FP32
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ float val(const P& a, const P& b) const { return static_cast<float>(A[a.i + b.i * lda]); }
+    using Pre = double;
+    __device__ Pre pre(const P& a, int64_t j) const { return A[a.i + j * lda]; }
+    __device__ float fin(const P&, Pre v) const { return static_cast<float>(v); }
 };
 
 struct DenseTSrc32 {  // (A*)(i, j) = A[j + i*lda], rounded to FP32
@@ -81,6 +88,9 @@ struct DenseTSrc32 {  // (A*)(i, j) = A[j + i*lda], rounded to FP32
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ float val(const P& a, const P& b) const { return static_cast<float>(A[b.i + a.i * lda]); }
+    using Pre = double;
+    __device__ Pre pre(const P& a, int64_t j) const { return A[j + a.i * lda]; }
+    __device__ float fin(const P&, Pre v) const { return static_cast<float>(v); }
 };
 
 template <int PREC>
@@ -193,13 +203,22 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
             if (ch < NCH) *reinterpret_cast<uint4*>(&sB[buf][ch * CH_EL]) = bv[u];
         }
     };
+    // the next step's kernel columns are loaded before the current step's MFMAs
+    // (pre) and turned into entries after them (gen_a)
+    typename AS::Pre apre[4];
+    auto pre_a = [&](int64_t jb, int64_t jend) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = jb + akk + 8 * u;
+            apre[u] = A.pre(rp, j < jend ? j : jend - 1);
+        }
+    };
     auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int kk = akk + 8 * u;
-            const int64_t j = jb + kk;
-            const float v = A.val(rp, A.col(j < jend ? j : jend - 1));
-            sA[buf][arow * AST + kk] = j < jend ? v : 0.0f;
+            const float v = A.fin(rp, apre[u]);
+            sA[buf][arow * AST + kk] = jb + kk < jend ? v : 0.0f;
         }
     };
 
@@ -214,15 +233,19 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
     int l = 0;
     int64_t j0 = box_ptr[0], jend = box_ptr[1];
     int64_t t = 0;  // packed step index
+    float tw[SPW], twn[SPW];
+    auto load_tw = [&](float* w, int lb) {
+#pragma unroll
+        for (int v = 0; v < SPW; ++v) w[v] = Tf[static_cast<int64_t>(lb) * ell + min(s_lo + v, ell - 1)];
+    };
     fetch_b(t);
+    pre_a(j0, jend);
+    load_tw(tw, 0);
     store_b(0);
     gen_a(0, j0, jend);
     __syncthreads();
     int buf = 0;
     for (;;) {
-        float tw[SPW];
-#pragma unroll
-        for (int v = 0; v < SPW; ++v) tw[v] = Tf[static_cast<int64_t>(l) * ell + min(s_lo + v, ell - 1)];
         int ln = l;
         int64_t jn = j0 + KT, jendn = jend;
         if (jn >= jend) {
@@ -233,7 +256,11 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
             }
         }
         const bool more = ln < nbox;
-        if (more) fetch_b(t + 1);
+        if (more) {
+            fetch_b(t + 1);
+            pre_a(jn, jendn);
+            load_tw(twn, ln);
+        }
         // this wave's A fragment: row rt*16 + lane % 16, sources 8 (lane / 16) + e
         float af[8];
         {
@@ -300,6 +327,8 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
         j0 = jn;
         jend = jendn;
         ++t;
+#pragma unroll
+        for (int v = 0; v < SPW; ++v) tw[v] = twn[v];
     }
     // epilogue: acc[v][sd][nt] element q -> row rt*16 + 4 (lane / 16) + q, column nt*16 + lane % 16
 #pragma unroll
