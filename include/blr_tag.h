@@ -163,6 +163,26 @@ blr_status blr_op_dense_create(int64_t n, const double* A, int64_t lda, blr_oper
  */
 blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const double* pts,
                                 blr_operator** out);
+
+/*
+ * The caller's products with A and A* (Section 2, the black-box setting of the
+ * problem statement): apply must enqueue Y = A X (trans = 0) or Y = A* X
+ * (trans = 1) on `stream`, X: n x ncols device memory (ldx >= n), Y likewise
+ * (ldy >= n), and return 0, or nonzero on failure (reported as
+ * BLR_ERR_OPERATOR).  It is called from the thread that called the library.
+ */
+typedef int32_t (*blr_apply_fn)(void* ctx, int32_t trans, int64_t ncols, const double* X,
+                                int64_t ldx, double* Y, int64_t ldy, void* stream);
+
+/*
+ * Black-box operator: every stage forms its test matrix explicitly and calls
+ * apply -- 2 ell r columns for the sketches (Alg. 2), b k for the cores
+ * (Table 1 step 2, in chunks of boxes) and 3^d m_max for the near-field
+ * probes (Table 1 step 3).  ctx is borrowed and must outlive the operator.
+ * The mixed-precision modes and blr_error_fro (which need entry access) return
+ * BLR_ERR_UNSUPPORTED for such operators.
+ */
+blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_operator** out);
 void blr_op_destroy(blr_operator* op);
 
 /*
@@ -353,6 +373,13 @@ typedef enum blr_ublr_part {
 /* Device pointer and element count of one part (the handle keeps ownership);
  * elements are double except for BLR_PART_Y0 and BLR_PART_Z0 (float). */
 blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count);
+
+/*
+ * Copies one part to host memory (element type and count as for
+ * blr_ublr_part_ptr; `count` must equal the part's count).  Waits for the
+ * copy on `stream` before returning.
+ */
+blr_status blr_ublr_export(const blr_ublr* h, int32_t part, void* host, int64_t count, void* stream);
 
 /*
  * y = A_uBLR x = U (Atil (V* x)) + B x (trans = 0) or A_uBLR* x (trans = 1)

@@ -50,6 +50,10 @@ class Report(ctypes.Structure):
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
+# int32 apply(ctx, trans, ncols, X, ldx, Y, ldy, stream): the black-box operator callback
+APPLY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                            c_void_p)
+
 # name -> (restype, argtypes); every symbol declared in include/blr_tag.h
 SIGNATURES = {
     "blr_status_string": (c_char_p, [c_int32]),
@@ -63,6 +67,7 @@ SIGNATURES = {
     "blr_plan_tags": (c_int32, [c_void_p, P_f64, P_f64]),
     "blr_op_dense_create": (c_int32, [c_int64, c_void_p, c_int64, POINTER(c_void_p)]),
     "blr_op_kernel_create": (c_int32, [c_int32, c_int32, c_int64, P_f64, POINTER(c_void_p)]),
+    "blr_op_callback_create": (c_int32, [c_int64, APPLY_FN, c_void_p, POINTER(c_void_p)]),
     "blr_op_destroy": (None, [c_void_p]),
     "blr_op_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                c_void_p]),
@@ -83,6 +88,7 @@ SIGNATURES = {
                                    c_void_p, POINTER(c_void_p), POINTER(Report)]),
     "blr_ublr_destroy": (None, [c_void_p]),
     "blr_ublr_part_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), P_i64]),
+    "blr_ublr_export": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "blr_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p]),
     "blr_error_fro": (c_int32, [c_void_p, c_void_p, c_void_p, P_f64]),

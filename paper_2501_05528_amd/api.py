@@ -44,10 +44,10 @@ def colmajor(a, device=None):
 class _DeviceView:
     """Column-major (rows x cols) float64 (or float32) device memory owned by the library."""
 
-    def __init__(self, ptr: int, rows: int, cols: int, itemsize: int = 8):
+    def __init__(self, ptr: int, rows: int, cols: int, itemsize: int = 8, ld: int = 0):
         self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": f"<f{itemsize}",
                                          "data": (ptr, False), "version": 2,
-                                         "strides": (itemsize, itemsize * rows)}
+                                         "strides": (itemsize, itemsize * max(ld, rows))}
 
 
 def colmajor_copy(t):
@@ -160,6 +160,35 @@ class Operator:
                                          p.ctypes.data_as(_lib.P_f64), byref(h)))
         return cls(h, p.shape[0])
 
+    @classmethod
+    def from_matmat(cls, n: int, matmat):
+        """A black-box operator from the caller's products: ``matmat(X, trans)`` gets a
+        column-major CUDA float64 tensor X (n x ncols) and returns A X (or A* X when
+        ``trans``) as a tensor of the same shape.  The library calls it on its stream
+        (made current here) for every product it needs."""
+        torch = _torch()
+
+        def _apply(ctx, trans, ncols, xp, ldx, yp, ldy, stream):
+            try:
+                X = torch.as_tensor(_DeviceView(xp, n, ncols, 8, ldx), device="cuda")
+                Y = torch.as_tensor(_DeviceView(yp, n, ncols, 8, ldy), device="cuda")
+                if stream:
+                    with torch.cuda.stream(torch.cuda.ExternalStream(stream)):
+                        Y.copy_(matmat(X, bool(trans)))
+                else:
+                    # the library runs on the null stream: torch's work on its default
+                    # stream is not ordered before the library's next step, so wait here
+                    Y.copy_(matmat(X, bool(trans)))
+                    torch.cuda.synchronize()
+                return 0
+            except Exception:  # reported to the caller as BLR_ERR_OPERATOR
+                return 1
+
+        fn = _lib.APPLY_FN(_apply)
+        h = c_void_p()
+        check(lib().blr_op_callback_create(n, fn, None, byref(h)))
+        return cls(h, n, keep=fn)
+
     def apply(self, X, trans: bool = False, stream=None):
         Y = colmajor_empty(self.n, X.shape[1], X.device)
         check(lib().blr_op_apply(self._h, 1 if trans else 0, X.shape[1], _ptr(X), _ld(X), _ptr(Y),
@@ -203,6 +232,14 @@ class UBLR:
         view = torch.as_tensor(_DeviceView(ptr, rows, cols, itemsize), device="cuda")
         return view.clone(memory_format=torch.preserve_format) if cols == 1 else \
             colmajor_copy(view)
+
+    def export(self, name: str, stream=None):
+        """A host (numpy) copy of one part, matrices column-major (Fortran order)."""
+        _, cnt = self.part_ptr(name)
+        dt = np.float32 if name in ("Y0", "Z0") else np.float64
+        out = np.empty(cnt, dtype=dt)
+        check(lib().blr_ublr_export(self._h, PARTS[name], out.ctypes.data_as(c_void_p), cnt, _stream(stream)))
+        return out
 
     def apply(self, x, trans: bool = False, stream=None):
         y = colmajor_empty(self.plan.n, x.shape[1], x.device)

@@ -62,16 +62,27 @@ double* dalloc_sync(int64_t count) {
 }
 
 // Frees stream-ordered temporaries when a call leaves (normally or by error).
+// Buffers handed to a caller's apply callback come from plain(): ordinary device
+// allocations rather than stream-ordered pool memory, so that any framework the
+// callback uses can wrap them.
 struct AsyncTemps {
     hipStream_t s;
-    std::vector<double*> ptrs;
+    std::vector<double*> ptrs, plain_ptrs;
     explicit AsyncTemps(hipStream_t st) : s(st) {}
     double* get(int64_t count) {
         ptrs.push_back(dalloc(count, s));
         return ptrs.back();
     }
+    double* plain(int64_t count) {
+        plain_ptrs.push_back(dalloc_sync(count));
+        return plain_ptrs.back();
+    }
     ~AsyncTemps() {
         for (double* p : ptrs) (void)hipFreeAsync(p, s);
+        if (!plain_ptrs.empty()) {
+            (void)hipStreamSynchronize(s);
+            for (double* p : plain_ptrs) (void)hipFree(p);
+        }
     }
 };
 
@@ -118,6 +129,86 @@ void check_ld(int64_t ld, int64_t n, const char* what) {
     if (ld < n) fail(BLR_ERR_INVALID_ARG, std::string(what) + " leading dimension is smaller than N");
 }
 
+// ---- operator dispatch: built-in operators run fused kernels; a black-box
+// operator gets explicit test matrices and the caller's products.
+bool is_callback(const OpData& o) { return o.type == OpType::Callback; }
+
+void require_entries(const OpData& o, const char* what) {
+    if (is_callback(o))
+        fail(BLR_ERR_UNSUPPORTED, std::string(what) + " needs entry access, which a black-box operator does not give");
+}
+
+void op_apply(const OpData& o, int trans, int64_t ncols, const double* X, int64_t ldx, double* Y,
+              int64_t ldy, hipStream_t s) {
+    if (!is_callback(o)) {
+        launch_op_apply(o, trans, ncols, X, ldx, Y, ldy, s);
+        return;
+    }
+    const int32_t rc = o.fn(o.ctx, trans, ncols, X, ldx, Y, ldy, static_cast<void*>(s));
+    if (rc != 0) {
+        std::ostringstream os;
+        os << "operator apply returned " << rc;
+        fail(BLR_ERR_OPERATOR, os.str());
+    }
+}
+
+// Columns of a block-diagonal test matrix per call: about 2^27 doubles (1 GiB).
+int boxes_per_chunk(const PlanData& P, int w) {
+    const int64_t per_box = P.n * static_cast<int64_t>(std::max(1, w));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(P.b, (int64_t(1) << 27) / per_box)));
+}
+
+void sketch_any(const OpData& o, const PlanData& P, const DeviceTables& t, const double* G,
+                const double* H, double* Y, double* Z, hipStream_t s, AsyncTemps& tmp) {
+    if (!is_callback(o)) {
+        launch_sketch(o, P, t, G, H, Y, Z, s);
+        return;
+    }
+    const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+    double* Om = tmp.plain(P.n * LR);
+    double* Yo = tmp.plain(P.n * LR);
+    launch_expand_tagged(P, t, G, Om, s);
+    op_apply(o, 0, LR, Om, P.n, Yo, P.n, s);
+    HIPC(hipMemcpyAsync(Y, Yo, P.n * LR * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_expand_tagged(P, t, H, Om, s);
+    op_apply(o, 1, LR, Om, P.n, Yo, P.n, s);
+    HIPC(hipMemcpyAsync(Z, Yo, P.n * LR * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+void cores_any(const OpData& o, const PlanData& P, const DeviceTables& t, const double* U,
+               const double* V, double* Atil, hipStream_t s, AsyncTemps& tmp) {
+    if (!is_callback(o)) {
+        launch_cores(o, P, t, U, V, Atil, s);
+        return;
+    }
+    const int cb = boxes_per_chunk(P, P.k);
+    double* X = tmp.plain(P.n * static_cast<int64_t>(cb) * P.k);
+    double* W = tmp.plain(P.n * static_cast<int64_t>(cb) * P.k);
+    for (int j0 = 0; j0 < P.b; j0 += cb) {
+        const int j1 = std::min(P.b, j0 + cb);
+        launch_embed_blockdiag(P, t, V, P.k, j0, j1, X, s);
+        op_apply(o, 0, static_cast<int64_t>(j1 - j0) * P.k, X, P.n, W, P.n, s);
+        launch_cores_from_w(P, t, U, W, j0, j1, Atil, s);
+    }
+}
+
+void nearfield_any(const OpData& o, const PlanData& P, const DeviceTables& t, const double* U,
+                   const double* V, const double* Atil, double* Bv, hipStream_t s, AsyncTemps& tmp) {
+    double* work = tmp.get(nearfield_workspace_doubles(P));
+    if (!is_callback(o)) {
+        launch_nearfield(o, P, t, U, V, Atil, Bv, work, s);
+        return;
+    }
+    launch_nf_q(P, t, V, Atil, work, s);
+    double* X = tmp.plain(P.n * static_cast<int64_t>(P.m_max));
+    double* Pc = tmp.plain(P.n * static_cast<int64_t>(P.m_max));
+    for (int c = 0; c < P.ncol; ++c) {
+        launch_identity_probe(P, t, c, X, s);
+        op_apply(o, 0, P.m_max, X, P.n, Pc, P.n, s);
+        launch_nf_from_probe(P, t, Pc, c, U, work, Bv, s);
+    }
+}
+
 }  // namespace
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -138,6 +229,7 @@ void DeviceTables::release() {
     dfree(kstep_ptr);
     dfree(kstep_box);
     dfree(nearm);
+    dfree(colour);
 }
 
 const DeviceTables& PlanData::tables() {
@@ -170,6 +262,7 @@ const DeviceTables& PlanData::tables() {
         t->kstep_ptr = upload(kstep_ptr);
         t->kstep_box = upload(kstep_box);
         t->nearm = upload(nearm);
+        t->colour = upload(colour);
     } catch (...) {
         t->release();
         throw;
@@ -344,6 +437,23 @@ blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const doub
     });
 }
 
+blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_operator** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out || !apply) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (n <= 0) fail(BLR_ERR_INVALID_ARG, "need n > 0");
+        auto d = std::make_unique<OpData>();
+        d->type = OpType::Callback;
+        d->n = n;
+        d->fn = apply;
+        d->ctx = ctx;
+        d->device = current_device();
+        auto* o = new blr_operator;
+        o->d = std::move(d);
+        *out = o;
+    });
+}
+
 void blr_op_destroy(blr_operator* op) { delete op; }
 
 blr_status blr_op_apply(const blr_operator* op, int32_t trans, int64_t ncols, const double* X,
@@ -357,7 +467,7 @@ blr_status blr_op_apply(const blr_operator* op, int32_t trans, int64_t ncols, co
         check_ld(ldx, o.n, "X");
         check_ld(ldy, o.n, "Y");
         if (o.device != current_device()) fail(BLR_ERR_INVALID_ARG, "operator belongs to another device");
-        launch_op_apply(o, trans ? 1 : 0, ncols, X, ldx, Y, ldy, static_cast<hipStream_t>(stream));
+        op_apply(o, trans ? 1 : 0, ncols, X, ldx, Y, ldy, static_cast<hipStream_t>(stream));
     });
 }
 
@@ -368,7 +478,9 @@ blr_status blr_sketch(const blr_plan* plan, const blr_operator* op, const double
         const OpData& o = op_of(op, P);
         if (!G || !H || !Y || !Z) fail(BLR_ERR_INVALID_ARG, "NULL G, H, Y or Z");
         const DeviceTables& t = plan->d->tables();
-        launch_sketch(o, P, t, G, H, Y, Z, static_cast<hipStream_t>(stream));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        AsyncTemps tmp(s);
+        sketch_any(o, P, t, G, H, Y, Z, s, tmp);
     });
 }
 
@@ -402,7 +514,9 @@ blr_status blr_cores(const blr_plan* plan, const blr_operator* op, const double*
         const OpData& o = op_of(op, P);
         if (!U || !V || !Atil) fail(BLR_ERR_INVALID_ARG, "NULL U, V or Atil");
         const DeviceTables& t = plan->d->tables();
-        launch_cores(o, P, t, U, V, Atil, static_cast<hipStream_t>(stream));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        AsyncTemps tmp(s);
+        cores_any(o, P, t, U, V, Atil, s, tmp);
     });
 }
 
@@ -415,8 +529,7 @@ blr_status blr_nearfield(const blr_plan* plan, const blr_operator* op, const dou
         const DeviceTables& t = plan->d->tables();
         hipStream_t s = static_cast<hipStream_t>(stream);
         AsyncTemps tmp(s);
-        double* work = tmp.get(nearfield_workspace_doubles(P));
-        launch_nearfield(o, P, t, U, V, Atil, Bvals, work, s);
+        nearfield_any(o, P, t, U, V, Atil, Bvals, s, tmp);
     });
 }
 
@@ -464,6 +577,7 @@ blr_status blr_sketch_lowp(const blr_plan* plan, const blr_operator* op, int32_t
         const PlanData& P = plan_of(plan);
         const OpData& o = op_of(op, P);
         if (!is_mixed(precision)) fail(BLR_ERR_INVALID_ARG, "precision must be a mixed mode");
+        require_entries(o, "the low-precision sketch");
         check_r_lo(P, r_lo);
         if (!G || !H || !Y0 || !Z0) fail(BLR_ERR_INVALID_ARG, "NULL G, H, Y0 or Z0");
         const DeviceTables& t = plan->d->tables();
@@ -508,6 +622,7 @@ blr_status blr_refine_sketch(const blr_plan* plan, const blr_operator* op, int32
         const OpData& o = op_of(op, P);
         check_r_lo(P, r_lo);
         if (!U0 || !V0 || !gamma_u || !gamma_v || !SY || !SZ) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        require_entries(o, "the refinement sketch");
         const DeviceTables& t = plan->d->tables();
         hipStream_t s = static_cast<hipStream_t>(stream);
         AsyncTemps tmp(s);
@@ -538,6 +653,7 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         if (mixed) {
             check_r_lo(P, r_lo);
             if (!O.gamma_u || !O.gamma_v) fail(BLR_ERR_INVALID_ARG, "mixed modes need gamma_u and gamma_v");
+            require_entries(o, "the mixed-precision modes");
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         const DeviceTables& t = plan->d->tables();
@@ -581,7 +697,7 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
             double* Yh = tmp.get(P.n * P.r);
             double* Zh = tmp.get(P.n * P.r);
             mark(0);
-            launch_sketch(o, P, t, G, H, Y, Z, s);
+            sketch_any(o, P, t, G, H, Y, Z, s, tmp);
             mark(1);
             launch_postprocess(P, t, Y, Yh, s);
             launch_postprocess(P, t, Z, Zh, s);
@@ -640,9 +756,9 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
             launch_orth2(P, t, SY, SZ, h->U, h->V, nullptr, nullptr, s);
         }
         mark(5);
-        launch_cores(o, P, t, h->U, h->V, h->Atil, s);
+        cores_any(o, P, t, h->U, h->V, h->Atil, s, tmp);
         mark(6);
-        launch_nearfield(o, P, t, h->U, h->V, h->Atil, h->B, tmp.get(nearfield_workspace_doubles(P)), s);
+        nearfield_any(o, P, t, h->U, h->V, h->Atil, h->B, s, tmp);
         mark(7);
         if (timing) {
             HIPC(hipStreamSynchronize(s));
@@ -711,6 +827,21 @@ blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, 
     });
 }
 
+blr_status blr_ublr_export(const blr_ublr* h, int32_t part, void* host, int64_t count, void* stream) {
+    return guard([&] {
+        if (!host) fail(BLR_ERR_INVALID_ARG, "NULL host buffer");
+        const void* ptr = nullptr;
+        int64_t cnt = 0;
+        const blr_status st = blr_ublr_part_ptr(h, part, &ptr, &cnt);
+        if (st != BLR_OK) fail(st, g_last_error);
+        if (count != cnt) fail(BLR_ERR_INVALID_ARG, "count differs from the part's element count");
+        const size_t esize = (part == BLR_PART_Y0 || part == BLR_PART_Z0) ? sizeof(float) : sizeof(double);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        HIPC(hipMemcpyAsync(host, ptr, static_cast<size_t>(cnt) * esize, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    });
+}
+
 blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x, int64_t ldx,
                      double* y, int64_t ldy, void* stream) {
     return guard([&] {
@@ -743,6 +874,7 @@ blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream
         AsyncTemps tmp(s);
         const int64_t np = static_cast<int64_t>(P.b) * P.b;
         double* part = tmp.get(2 * np);
+        require_entries(o, "the exact Frobenius error");
         launch_err_fro(o, P, t, d.U, d.V, d.Atil, d.B, part, s);
         std::vector<double> hp(2 * np);
         HIPC(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -768,9 +900,11 @@ blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const doub
         const DeviceTables& t = d.plan->tables();
         const int64_t n = P.n;
         AsyncTemps tmp(s);
-        double* x = tmp.get(n);
-        double* y = tmp.get(n);
-        double* w = tmp.get(n);
+        // x, y, w are operands of the operator's products (plain allocations for a callback)
+        const bool cb = is_callback(o);
+        double* x = cb ? tmp.plain(n) : tmp.get(n);
+        double* y = cb ? tmp.plain(n) : tmp.get(n);
+        double* w = cb ? tmp.plain(n) : tmp.get(n);
         double* u = tmp.get(n);
         double* part = tmp.get(dot_parts());
         double* work = tmp.get(apply_workspace_doubles(P, 1));
@@ -783,7 +917,7 @@ blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const doub
         };
         // M v = A v - (use_ublr ? A_uBLR v : 0); M* likewise
         auto apply_M = [&](int trans, bool diff, const double* in, double* out) {
-            launch_op_apply(o, trans, 1, in, n, out, n, s);
+            op_apply(o, trans, 1, in, n, out, n, s);
             if (diff) {
                 launch_ublr_apply(P, t, d.U, d.V, d.Atil, d.B, trans, 1, in, n, u, n, work, s);
                 launch_axpy(-1.0, u, out, n, s);

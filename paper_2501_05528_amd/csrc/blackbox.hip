@@ -1,0 +1,184 @@
+// Kernels for operators given only by products with A and A* (the paper's
+// black-box setting): the library forms the test matrices of each step
+// explicitly, the caller's apply callback multiplies them, and these kernels
+// turn the products into Atil and B (Table 1, reconstruct_tag).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace blr {
+namespace {
+
+void check_launch_bb(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(BLR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Omega(row, s*r + c) = T(box(row), s) G(row, c)  (eq. extend_test_mat), N x ell r.
+__global__ __launch_bounds__(256) void k_expand_tagged(const double* __restrict__ G, int64_t n, int r,
+                                                       int ell, const double* __restrict__ T,
+                                                       const int32_t* __restrict__ rb,
+                                                       double* __restrict__ Om) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = n * static_cast<int64_t>(ell) * r;
+    if (idx >= total) return;
+    const int64_t col = idx / n;
+    const int64_t row = idx - col * n;
+    const int s = static_cast<int>(col / r), c = static_cast<int>(col - static_cast<int64_t>(s) * r);
+    Om[idx] = T[static_cast<int64_t>(rb[row]) * ell + s] * G[row + static_cast<int64_t>(c) * n];
+}
+
+// X(:, (j - j0) w + t) = S(:, t) on the rows of box j, zero elsewhere, for boxes
+// j0 <= j < j1 (a column chunk of blkdiag(S_1, ..., S_b) with w columns per box).
+__global__ __launch_bounds__(256) void k_embed_blockdiag(const double* __restrict__ S, int64_t n, int w,
+                                                         const int32_t* __restrict__ rb, int j0, int j1,
+                                                         double* __restrict__ X) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t ncols = static_cast<int64_t>(j1 - j0) * w;
+    if (idx >= n * ncols) return;
+    const int64_t col = idx / n;
+    const int64_t row = idx - col * n;
+    const int j = j0 + static_cast<int>(col / w), t = static_cast<int>(col % w);
+    X[idx] = rb[row] == j ? S[row + static_cast<int64_t>(t) * n] : 0.0;
+}
+
+// X_c(box_ptr[l] + u, u) = 1 for every box l of colour c and u < m_l, zero elsewhere
+// (the sparse identity probe of Table 1 step 3), N x m_max.
+__global__ __launch_bounds__(256) void k_identity_probe(int64_t n, int m_max, const int32_t* __restrict__ rb,
+                                                        const int64_t* __restrict__ box_ptr,
+                                                        const int32_t* __restrict__ colour, int c,
+                                                        double* __restrict__ X) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= n * m_max) return;
+    const int64_t col = idx / n;
+    const int64_t row = idx - col * n;
+    const int l = rb[row];
+    X[idx] = (colour[l] == c && row - box_ptr[l] == col) ? 1.0 : 0.0;
+}
+
+// Atil(i k + a, j k + t) = sum_{row in I_i} U(row, a) W(row, (j - j0) k + t) for the
+// boxes j0 <= j < j1 of one chunk: U_i* (A V)(I_i, J_j) (Table 1 step 2).  One
+// workgroup per (row box i, 64-column tile of the chunk); rows staged in LDS.
+__global__ __launch_bounds__(256) void k_cores_from_w(const double* __restrict__ U, int64_t n, int k,
+                                                      const int64_t* __restrict__ box_ptr,
+                                                      const double* __restrict__ W, int64_t ncols,
+                                                      int j0, double* __restrict__ Atil, int64_t ldAt) {
+    constexpr int RT = 16, CT = 64;
+    __shared__ double sU[RT][64];
+    __shared__ double sW[RT][CT];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * CT;
+    const int64_t ri0 = box_ptr[i];
+    const int mi = static_cast<int>(box_ptr[i + 1] - ri0);
+    const int cc = tid % CT;            // tile column
+    const int ab = tid / CT;            // rows a = ab, ab + 4, ...
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int a0 = 0; a0 < mi; a0 += RT) {
+        __syncthreads();
+        for (int e = tid; e < RT * 64; e += 256) {
+            const int rr = e / 64, a = e % 64;
+            sU[rr][a] = (a0 + rr < mi && a < k) ? U[ri0 + a0 + rr + static_cast<int64_t>(a) * n] : 0.0;
+        }
+        for (int e = tid; e < RT * CT; e += 256) {
+            const int rr = e / CT, q = e % CT;
+            sW[rr][q] = (a0 + rr < mi && c0 + q < ncols) ? W[ri0 + a0 + rr + (c0 + q) * n] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int rr = 0; rr < RT; ++rr) {
+            const double w = sW[rr][cc];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += sU[rr][ab + 4 * q] * w;
+        }
+    }
+    if (c0 + cc < ncols) {
+        const int64_t col = static_cast<int64_t>(j0) * k + c0 + cc;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int a = ab + 4 * q;
+            if (a < k) Atil[static_cast<int64_t>(i) * k + a + col * ldAt] = acc[q];
+        }
+    }
+}
+
+// B_il(a, col) = P_c(I_i[a], col) - sum_t U_i(a, t) Q_ic(col, t) for the neighbour l of
+// box i that has colour c (Table 1 step 3, with P_c = A X_c from the caller's apply and
+// Q_ic = X_c^T V Atil_{i,:}^T from the near-field workspace).
+__global__ __launch_bounds__(256) void k_nf_from_probe(const double* __restrict__ Pc, int64_t ldP,
+                                                       int c, const int64_t* __restrict__ box_ptr,
+                                                       const int32_t* __restrict__ near_idx,
+                                                       const int64_t* __restrict__ b_off,
+                                                       const int32_t* __restrict__ nf_pair, int ncol,
+                                                       const double* __restrict__ U, int64_t ldUV, int k,
+                                                       int m_max, int kp, const double* __restrict__ Qg,
+                                                       double* __restrict__ Bv) {
+    const int i = blockIdx.x;
+    const int pair = i * ncol + c;
+    const int p = nf_pair[pair];
+    if (p < 0) return;
+    const int l = near_idx[p];
+    const int64_t ri0 = box_ptr[i];
+    const int mi = static_cast<int>(box_ptr[i + 1] - ri0);
+    const int ml = static_cast<int>(box_ptr[l + 1] - box_ptr[l]);
+    const double* Q = Qg + static_cast<int64_t>(pair) * m_max * kp;
+    double* Bout = Bv + b_off[p];
+    for (int64_t e = threadIdx.x; e < static_cast<int64_t>(mi) * ml; e += 256) {
+        const int col = static_cast<int>(e / mi), a = static_cast<int>(e % mi);
+        double v = Pc[ri0 + a + static_cast<int64_t>(col) * ldP];
+        for (int t = 0; t < k; ++t) v -= U[ri0 + a + static_cast<int64_t>(t) * ldUV] * Q[static_cast<int64_t>(col) * kp + t];
+        Bout[a + static_cast<int64_t>(col) * mi] = v;
+    }
+}
+
+unsigned blocks_for(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
+
+}  // namespace
+
+void launch_expand_tagged(const PlanData& P, const DeviceTables& t, const double* G, double* Om,
+                          hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(P.ell) * P.r;
+    hipLaunchKernelGGL(k_expand_tagged, dim3(blocks_for(total)), dim3(256), 0, s, G, P.n, P.r, P.ell, t.T,
+                       t.row_box, Om);
+    check_launch_bb("tagged test matrix");
+}
+
+void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const double* S, int w, int j0,
+                            int j1, double* X, hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(j1 - j0) * w;
+    hipLaunchKernelGGL(k_embed_blockdiag, dim3(blocks_for(total)), dim3(256), 0, s, S, P.n, w, t.row_box,
+                       j0, j1, X);
+    check_launch_bb("block-diagonal test columns");
+}
+
+void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(P.m_max);
+    hipLaunchKernelGGL(k_identity_probe, dim3(blocks_for(total)), dim3(256), 0, s, P.n, P.m_max, t.row_box,
+                       t.box_ptr, t.colour, c, X);
+    check_launch_bb("identity probe");
+}
+
+void launch_cores_from_w(const PlanData& P, const DeviceTables& t, const double* U, const double* W,
+                         int j0, int j1, double* Atil, hipStream_t s) {
+    if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "k > 64 is not supported by the cores kernel");
+    const int64_t ncols = static_cast<int64_t>(j1 - j0) * P.k;
+    const dim3 grid(P.b, static_cast<unsigned>((ncols + 63) / 64));
+    hipLaunchKernelGGL(k_cores_from_w, grid, dim3(256), 0, s, U, P.n, P.k, t.box_ptr, W, ncols, j0, Atil,
+                       static_cast<int64_t>(P.b) * P.k);
+    check_launch_bb("cores from products");
+}
+
+void launch_nf_from_probe(const PlanData& P, const DeviceTables& t, const double* Pc, int c,
+                          const double* U, const double* Qwork, double* Bv, hipStream_t s) {
+    const int kp = 16 * ((P.k + 15) / 16);
+    hipLaunchKernelGGL(k_nf_from_probe, dim3(P.b), dim3(256), 0, s, Pc, P.n, c, t.box_ptr, t.near_idx,
+                       t.b_off, t.nf_pair, P.ncol, U, P.n, P.k, P.m_max, kp, Qwork, Bv);
+    check_launch_bb("near field from probes");
+}
+
+}  // namespace blr

@@ -41,6 +41,7 @@ struct DeviceTables {
     int32_t* kstep_ptr = nullptr;    // [b+1] first 32-row source step of each box
     int32_t* kstep_box = nullptr;    // [nsteps] box of each 32-row source step
     uint8_t* nearm = nullptr;        // [b*b] 1 if box j is in N_i (i-major)
+    int32_t* colour = nullptr;       // [b] probe colour of each box
     void release();
 };
 
@@ -70,7 +71,7 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
 int tag_columns(const blr_geometry* g, int extra);
 
 // Operators.
-enum class OpType { Dense, Kernel };
+enum class OpType { Dense, Kernel, Callback };
 struct OpData {
     OpType type = OpType::Dense;
     int64_t n = 0;
@@ -80,6 +81,8 @@ struct OpData {
     int64_t lda = 0;
     double* pts = nullptr;        // kernel: device SoA [3][n] (unused axes zero), owned
     float* pts32 = nullptr;       // kernel: the same points in FP32, owned
+    blr_apply_fn fn = nullptr;    // callback: the caller's products with A and A*
+    void* ctx = nullptr;          // callback: the caller's context, borrowed
     int device = -1;
     ~OpData();
 };

@@ -1680,6 +1680,26 @@ void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t
     check_launch("near field");
 }
 
+void launch_nf_q(const PlanData& P, const DeviceTables& t, const double* V, const double* Atil,
+                 double* work, hipStream_t s) {
+    if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "k > 64 is not supported by the near-field kernel");
+    const int64_t ldAt = static_cast<int64_t>(P.b) * P.k;
+    const int kp = 16 * ((P.k + 15) / 16);
+    const dim3 grid(P.b * P.ncol);
+    auto run = [&](auto kpc) {
+        constexpr int KP = decltype(kpc)::value;
+        hipLaunchKernelGGL((k_nf_q<KP>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes,
+                           t.nf_pair, P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work);
+    };
+    switch (kp) {
+        case 16: run(std::integral_constant<int, 16>{}); break;
+        case 32: run(std::integral_constant<int, 32>{}); break;
+        case 48: run(std::integral_constant<int, 48>{}); break;
+        default: run(std::integral_constant<int, 64>{}); break;
+    }
+    check_launch("near field (Q)");
+}
+
 static int apply_nsplit(int64_t bk) { return static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, bk / 256))); }
 
 int64_t apply_workspace_doubles(const PlanData& P, int64_t ncols) {

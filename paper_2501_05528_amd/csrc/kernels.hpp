@@ -52,6 +52,21 @@ void launch_mix(const PlanData& P, const DeviceTables& t, int r_lo, const double
 void launch_refine(const OpData& op, const PlanData& P, const DeviceTables& t, const double* X0,
                    const double* X1, double* S0, double* S1, hipStream_t s);
 
+// Black-box operators (blackbox.hip): explicit test matrices for the caller's
+// products and the kernels that turn the products into Atil and B.
+void launch_expand_tagged(const PlanData& P, const DeviceTables& t, const double* G, double* Om,
+                          hipStream_t s);
+void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const double* S, int w, int j0,
+                            int j1, double* X, hipStream_t s);
+void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s);
+void launch_cores_from_w(const PlanData& P, const DeviceTables& t, const double* U, const double* W,
+                         int j0, int j1, double* Atil, hipStream_t s);
+void launch_nf_from_probe(const PlanData& P, const DeviceTables& t, const double* Pc, int c,
+                          const double* U, const double* Qwork, double* Bv, hipStream_t s);
+// First half of the near field: Q_ic = X_c^T V Atil_{i,:}^T into the workspace.
+void launch_nf_q(const PlanData& P, const DeviceTables& t, const double* V, const double* Atil,
+                 double* work, hipStream_t s);
+
 // Near field; work must hold nearfield_workspace_doubles(P) doubles.
 int64_t nearfield_workspace_doubles(const PlanData& P);
 void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
