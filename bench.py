@@ -173,6 +173,113 @@ def cpu_baseline(S, nsample_boxes=4):
                       f"({dt:.1f} s), extrapolated linearly to all row boxes"}
 
 
+def _job_inputs(P, torch, wl, precision):
+    """Plan, operator and device inputs of one generator job."""
+    g = wl.geometry()
+    ell = P.tag_columns(g.box_ptr, g.lattice, wl.extra_tag_cols)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    gu, gv = W.refinement_gammas(wl.seed, g.nboxes, wl.r, wl.r)
+    plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=wl.extra_tag_cols)
+    return dict(wl=wl, n=g.n, plan=plan, op=P.Operator.kernel(wl.kind, g.pts), G=P.colmajor(G),
+                H=P.colmajor(H), gamma_u=torch.as_tensor(gu, device="cuda"),
+                gamma_v=torch.as_tensor(gv, device="cuda"), precision=precision)
+
+
+def _kw(j):
+    return {} if j["precision"] == "fp64" else dict(precision=j["precision"], gamma_u=j["gamma_u"],
+                                                    gamma_v=j["gamma_v"])
+
+
+def batch_section(njobs=24, seed=20250104, n_lo=4096, n_hi=32768):
+    """Uneven batch (the batch generator: N, box shape, rank, kernel per job): FP32-sketch
+    mixed jobs in one batch (persistent sketch launches, HIP graph replay, autotuned
+    tiles) against plain FP64 compressions one at a time, with the accuracy of each."""
+    import torch
+    import paper_2501_05528_amd as P
+    wls = W.uneven_batch_jobs(njobs, seed, n_lo=n_lo, n_hi=n_hi)
+    jobs64 = [_job_inputs(P, torch, wl, "fp64") for wl in wls]
+    jobs32 = [dict(j, precision="fp32") for j in jobs64]
+    torch.cuda.synchronize()
+    # plain FP64, one at a time (warm-up on the first job)
+    P.compress(jobs64[0]["plan"], jobs64[0]["op"], jobs64[0]["G"], jobs64[0]["H"], report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs64 = [P.compress(j["plan"], j["op"], j["G"], j["H"], report=False)[0] for j in jobs64]
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    e64 = [h.error_fro(j["op"]) for h, j in zip(hs64, jobs64)]
+    del hs64
+    b = P.Batch(jobs32, graph=True, autotune=True)
+    rep_eager = b.run()
+    b.run()
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(3):
+        reps.append(b.run())
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / 3
+    emx = [b.result(q).error_fro(j["op"]) for q, j in enumerate(jobs32)]
+    ratio = max(e / max(f, 1e-300) for e, f in zip(emx, e64))
+    sk = rep_eager["sketch_flops"] / (rep_eager["ms_sketch"] * 1e-3) / 1e12 if rep_eager["ms_sketch"] else None
+    return {"jobs": njobs, "N_range": [min(j["n"] for j in jobs64), max(j["n"] for j in jobs64)],
+            "fp64_one_at_a_time_jobs_per_s": round(njobs / t64, 3),
+            "batched_fp32_jobs_per_s": round(njobs / tb, 3),
+            "speedup": round(t64 / tb, 3),
+            "max_err_ratio_vs_fp64": round(ratio, 4),
+            "max_rel_err_fro_fp64": max(e64), "max_rel_err_fro_batched": max(emx),
+            "graph_replay_ms": round(float(np.median([r["ms_total"] for r in reps])), 3),
+            "eager_ms": round(rep_eager["ms_total"], 3),
+            "eager_sketch_ms": round(rep_eager["ms_sketch"], 3),
+            "sketch_tflops_eager": round(sk, 2) if sk else None,
+            "sketch_classes": {"ntr": rep_eager["class_ntr"], "spw": reps[-1]["class_spw"],
+                               "jobs": rep_eager["class_jobs"]}}
+
+
+def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
+    """Poisson arrivals of a job mix (4 in 5 from the batch generator in the BF16 mixed
+    mode, 1 in 5 the 2D Laplace N = 65536, k = 32 job): a 4-slot server with HBM-budget
+    admission against plain FP64 one at a time (1 slot), same arrivals."""
+    import torch
+    import paper_2501_05528_amd as P
+    gen = W.uneven_batch_jobs(njobs, seed, n_lo=4096, n_hi=32768)
+    lap = _job_inputs(P, torch, W.WORKLOADS["laplace2d_n65536"], "bf16")
+    mix = []
+    for q, wl in enumerate(gen):
+        mix.append(lap if q % 5 == 4 else _job_inputs(P, torch, wl, "bf16"))
+    torch.cuda.synchronize()
+    rng = W.rng(seed, W.STREAM_ARRIVALS)
+
+    def drive(gaps, precision, slots):
+        srv = P.Server(hbm_budget=160 << 30, slots=slots)
+        tickets = []
+        t = time.monotonic()
+        t_first = t
+        for j, gap in zip(mix, gaps):
+            t += gap
+            while time.monotonic() < t:
+                time.sleep(0.0002)
+            jj = dict(j, precision=precision)
+            tickets.append(srv.submit(jj["plan"], jj["op"], jj["G"], jj["H"], **_kw(jj)))
+        lat, t_last = [], t_first
+        for tk in tickets:
+            _, st = srv.wait(tk)
+            lat.append(st["t_end"] - st["t_submit"])
+            t_last = max(t_last, st["t_end"])
+        srv.close()
+        return {"jobs_per_s": round(len(mix) / (t_last - t_first), 3),
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2)}
+
+    out = {"jobs": len(mix), "slots": 4, "admission": "FIFO by HBM footprint (160 GiB budget)"}
+    for rate in rates:
+        gaps = rng.exponential(1.0 / rate, size=len(mix))   # the same arrivals for both
+        out[f"rate_{int(rate)}"] = {"served_bf16": drive(gaps, "bf16", 4),
+                                    "fp64_one_at_a_time": drive(gaps, "fp64", 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +288,8 @@ def main():
     ap.add_argument("--workload", default="laplace2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-job measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (BF16 / FP32 sketch + FP64 refinement) runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -255,6 +364,18 @@ def main():
                                     "algorithmic_flops_per_launch": rp["refine_flops"]},
             }
         out["mixed"] = mixed
+    if not args.no_batch:
+        try:
+            log("batched uneven jobs")
+            out["batch"] = batch_section()
+        except Exception as e:  # extra measurement: never lose the line above
+            out["batch"] = {"error": repr(e)}
+    if not args.no_serve:
+        try:
+            log("serving with Poisson arrivals")
+            out["serve"] = serve_section()
+        except Exception as e:
+            out["serve"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(S)

@@ -406,6 +406,117 @@ blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream
 blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const double* x0,
                            int32_t iters, void* stream, double* err_norm, double* a_norm);
 
+/* ----------------------------------------------------- batches of compressions
+ * Many independent compressions of uneven N, box size, rank and kernel in one
+ * object (not in the paper: the batched form of Table 1's reconstruct_tag).
+ */
+
+/*
+ * Device bytes one blr_tag_compress call needs on `plan` in the given precision
+ * (r_lo as in blr_compress_opts, 0 means r): the handle's outputs U, V, Atil, B
+ * plus every temporary of the call.  Used for admission by HBM budget.
+ */
+blr_status blr_plan_footprint(const blr_plan* plan, int32_t precision, int32_t r_lo, int64_t* bytes);
+
+typedef struct blr_batch blr_batch;
+
+typedef struct blr_batch_job {
+    const blr_plan* plan;
+    const blr_operator* op;   /* built-in operator (dense or kernel); borrowed */
+    const double* G;          /* device N x r (FP64) or N x r_lo (mixed); borrowed */
+    const double* H;
+    blr_compress_opts opts;   /* precision, r_lo, gamma_u, gamma_v (device, borrowed) */
+} blr_batch_job;
+
+enum {
+    BLR_BATCH_GRAPH = 1,      /* capture the whole batch into a HIP graph on the second run
+                                 and replay it on every later run */
+    BLR_BATCH_AUTOTUNE = 2    /* first run: time each candidate tile shape of the persistent
+                                 sketch per class and keep the fastest (cached per device) */
+};
+
+typedef struct blr_batch_report {
+    double ms_total;          /* the batch on the device (events on the batch stream) */
+    double ms_sketch;         /* the low-precision sketch launches (0 when a graph is replayed) */
+    double sketch_flops;      /* sum over jobs of 4 N^2 ell r_lo (4 N^2 ell r for FP64 jobs) */
+    double refine_flops;      /* sum over mixed jobs of the refinement's far-field flops */
+    int64_t applies;          /* sum over jobs of the products in the paper's convention */
+    int32_t graph_replayed;   /* 1 if this run replayed the captured graph */
+    int32_t nclasses;         /* persistent sketch launches (one per precision and column tiles) */
+    int32_t class_precision[8], class_ntr[8], class_spw[8], class_jobs[8];
+} blr_batch_report;
+
+/*
+ * Plans the batch and allocates every output and temporary up front (no device
+ * allocation happens in blr_batch_run).  Mixed-precision kernel-matrix jobs share
+ * persistent sketch launches, one per (precision, 16-column tiles of r_lo) class,
+ * whose workgroups stride over (job, 32-row block, tag column group) items,
+ * heaviest first; every other stage runs per job.  Jobs on dense operators and
+ * FP64 jobs use the single-job sketch kernels.  Black-box (callback) operators
+ * are not supported (BLR_ERR_UNSUPPORTED).  flags: BLR_BATCH_GRAPH,
+ * BLR_BATCH_AUTOTUNE.
+ */
+blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t flags, blr_batch** out);
+
+/*
+ * Runs every compression of the batch on the batch's own stream, ordered after
+ * the work already on `stream`; `stream` waits for the batch.  Results (and the
+ * report) are valid after `stream` is synchronised.  Each job's arithmetic does not
+ * depend on the other jobs, so its results equal those of blr_tag_compress on the
+ * same inputs.
+ */
+blr_status blr_batch_run(blr_batch* b, void* stream, blr_batch_report* rep);
+
+/* The compressed handle of job `job` (owned by the batch, valid until destroy). */
+blr_status blr_batch_result(const blr_batch* b, int32_t job, const blr_ublr** h);
+
+void blr_batch_destroy(blr_batch* b);
+
+/* ------------------------------------------------------------ serving
+ * A request loop for compression jobs (not in the paper): jobs are admitted in
+ * arrival order as a slot and enough of the HBM budget are free, run
+ * concurrently on the slots' own streams, and complete independently.
+ */
+typedef struct blr_server blr_server;
+
+typedef struct blr_server_job_stats {
+    double t_submit, t_start, t_end;   /* host monotonic clock, seconds */
+    double ms_device;                  /* the job's compression on its stream (events) */
+    int64_t footprint;                 /* bytes charged against the budget */
+    int32_t slot;                      /* slot that ran the job */
+    int32_t status;                    /* blr_status of the job */
+} blr_server_job_stats;
+
+/*
+ * Creates a server on the current device with `slots` concurrent jobs (1..16, each
+ * with its own stream) and an HBM budget in bytes for the admitted jobs' footprints
+ * (blr_plan_footprint).
+ */
+blr_status blr_server_create(int64_t hbm_budget, int32_t slots, blr_server** out);
+
+/*
+ * Queues one compression (arguments as for blr_tag_compress; plan, op, G, H and
+ * the gamma arrays are borrowed until the job completes).  Returns BLR_ERR_BUSY if
+ * the job's footprint exceeds the whole budget.  *ticket identifies the job.
+ */
+blr_status blr_server_submit(blr_server* srv, const blr_plan* plan, const blr_operator* op,
+                             const double* G, const double* H, const blr_compress_opts* opts,
+                             uint64_t* ticket);
+
+/* *done = 1 once the job has completed (successfully or not). */
+blr_status blr_server_poll(blr_server* srv, uint64_t ticket, int32_t* done);
+
+/*
+ * Waits for the job, hands over its compressed handle (*out, owned by the caller;
+ * NULL if the job failed) and fills stats (nullable); returns the job's status.
+ * Each ticket can be waited for once.
+ */
+blr_status blr_server_wait(blr_server* srv, uint64_t ticket, blr_ublr** out,
+                           blr_server_job_stats* stats);
+
+/* Waits for every queued job, then releases the server (unclaimed handles are freed). */
+void blr_server_destroy(blr_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

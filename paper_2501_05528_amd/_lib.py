@@ -50,6 +50,27 @@ class Report(ctypes.Structure):
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
+class BatchJob(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("op", c_void_p), ("G", c_void_p), ("H", c_void_p),
+                ("opts", CompressOpts)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("ms_total", c_double), ("ms_sketch", c_double), ("sketch_flops", c_double),
+                ("refine_flops", c_double), ("applies", c_int64), ("graph_replayed", c_int32),
+                ("nclasses", c_int32), ("class_precision", c_int32 * 8), ("class_ntr", c_int32 * 8),
+                ("class_spw", c_int32 * 8), ("class_jobs", c_int32 * 8)]
+
+
+class ServerJobStats(ctypes.Structure):
+    _fields_ = [("t_submit", c_double), ("t_start", c_double), ("t_end", c_double),
+                ("ms_device", c_double), ("footprint", c_int64), ("slot", c_int32), ("status", c_int32)]
+
+
+BATCH_GRAPH = 1
+BATCH_AUTOTUNE = 2
+
+
 # int32 apply(ctx, trans, ncols, X, ldx, Y, ldy, stream): the black-box operator callback
 APPLY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p)
@@ -89,6 +110,17 @@ SIGNATURES = {
     "blr_ublr_destroy": (None, [c_void_p]),
     "blr_ublr_part_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), P_i64]),
     "blr_ublr_export": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
+    "blr_plan_footprint": (c_int32, [c_void_p, c_int32, c_int32, P_i64]),
+    "blr_batch_create": (c_int32, [c_int32, POINTER(BatchJob), c_int32, POINTER(c_void_p)]),
+    "blr_batch_run": (c_int32, [c_void_p, c_void_p, POINTER(BatchReport)]),
+    "blr_batch_result": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
+    "blr_batch_destroy": (None, [c_void_p]),
+    "blr_server_create": (c_int32, [c_int64, c_int32, POINTER(c_void_p)]),
+    "blr_server_submit": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(CompressOpts),
+                                    POINTER(ctypes.c_uint64)]),
+    "blr_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, P_i32]),
+    "blr_server_wait": (c_int32, [c_void_p, ctypes.c_uint64, POINTER(c_void_p), POINTER(ServerJobStats)]),
+    "blr_server_destroy": (None, [c_void_p]),
     "blr_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p]),
     "blr_error_fro": (c_int32, [c_void_p, c_void_p, c_void_p, P_f64]),

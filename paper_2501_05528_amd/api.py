@@ -205,11 +205,12 @@ class Operator:
 class UBLR:
     """Compressed A ~ U Atil V* + B owned by the library."""
 
-    def __init__(self, handle, plan: Plan, precision: str = "fp64", r_lo: int = 0):
+    def __init__(self, handle, plan: Plan, precision: str = "fp64", r_lo: int = 0, owner=None):
         self._h = handle
         self.plan = plan
         self.precision = precision
         self.r_lo = r_lo or plan.r
+        self._owner = owner        # a Batch that owns the handle (then it is not destroyed here)
 
     def part_ptr(self, name: str):
         ptr = c_void_p()
@@ -259,9 +260,113 @@ class UBLR:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "_owner", None) is None:
             lib().blr_ublr_destroy(h)
             self._h = None
+
+
+def footprint(plan: Plan, precision: str = "fp64", r_lo: int = 0) -> int:
+    """Device bytes of one compression on this plan (outputs and temporaries)."""
+    b = c_int64()
+    check(lib().blr_plan_footprint(plan._h, PRECISIONS[precision], r_lo, byref(b)))
+    return b.value
+
+
+class Batch:
+    """Many compressions in one object: persistent low-precision sketch launches across
+    jobs, optional HIP-graph replay and autotuned sketch tiles (blr_batch_*).
+
+    jobs: list of dicts with keys plan, op, G, H and, for mixed jobs, precision
+    ("bf16"/"fp32"), gamma_u, gamma_v (CUDA float64 tensors; kept alive here)."""
+
+    def __init__(self, jobs, graph: bool = False, autotune: bool = True):
+        arr = (_lib.BatchJob * len(jobs))()
+        self._keep = []
+        self._meta = []
+        for q, jb in enumerate(jobs):
+            prec = jb.get("precision", "fp64")
+            mixed = prec != "fp64"
+            G, H = jb["G"], jb["H"]
+            r_lo = G.shape[1] if mixed else 0
+            gu, gv = jb.get("gamma_u"), jb.get("gamma_v")
+            opts = _lib.CompressOpts(PRECISIONS[prec], 0, r_lo, 0, _ptr(gu).value if mixed else None,
+                                     _ptr(gv).value if mixed else None)
+            arr[q] = _lib.BatchJob(jb["plan"]._h.value, jb["op"]._h.value, _ptr(G).value, _ptr(H).value, opts)
+            self._keep.append((jb["plan"], jb["op"], G, H, gu, gv))
+            self._meta.append((jb["plan"], prec, r_lo))
+        flags = (_lib.BATCH_GRAPH if graph else 0) | (_lib.BATCH_AUTOTUNE if autotune else 0)
+        h = c_void_p()
+        check(lib().blr_batch_create(len(jobs), arr, flags, byref(h)))
+        self._h = h
+        self.njobs = len(jobs)
+
+    def run(self, stream=None):
+        rep = _lib.BatchReport()
+        check(lib().blr_batch_run(self._h, _stream(stream), byref(rep)))
+        out = {f: getattr(rep, f) for f, _ in _lib.BatchReport._fields_}
+        nc = rep.nclasses
+        for f in ("class_precision", "class_ntr", "class_spw", "class_jobs"):
+            out[f] = list(getattr(rep, f))[:nc]
+        return out
+
+    def result(self, j: int) -> UBLR:
+        h = c_void_p()
+        check(lib().blr_batch_result(self._h, j, byref(h)))
+        plan, prec, r_lo = self._meta[j]
+        return UBLR(h, plan, prec, r_lo, owner=self)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().blr_batch_destroy(h)
+            self._h = None
+
+
+class Server:
+    """Request loop for compression jobs (blr_server_*): FIFO admission by free slot and
+    HBM budget, concurrent slots on their own streams."""
+
+    def __init__(self, hbm_budget: int, slots: int = 4):
+        h = c_void_p()
+        check(lib().blr_server_create(int(hbm_budget), slots, byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, plan: Plan, op: Operator, G, H, precision: str = "fp64", gamma_u=None,
+               gamma_v=None) -> int:
+        mixed = precision != "fp64"
+        r_lo = G.shape[1] if mixed else 0
+        opts = _lib.CompressOpts(PRECISIONS[precision], 0, r_lo, 0, _ptr(gamma_u).value if mixed else None,
+                                 _ptr(gamma_v).value if mixed else None)
+        t = ctypes.c_uint64()
+        check(lib().blr_server_submit(self._h, plan._h, op._h, _ptr(G), _ptr(H), byref(opts), byref(t)))
+        self._pending[t.value] = (plan, op, G, H, gamma_u, gamma_v, precision, r_lo)
+        return t.value
+
+    def done(self, ticket: int) -> bool:
+        d = c_int32()
+        check(lib().blr_server_poll(self._h, ticket, byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        """(UBLR, stats dict); raises BlrError if the job failed."""
+        h = c_void_p()
+        st = _lib.ServerJobStats()
+        status = lib().blr_server_wait(self._h, ticket, byref(h), byref(st))
+        plan, op, G, H, gu, gv, prec, r_lo = self._pending.pop(ticket)
+        stats = {f: getattr(st, f) for f, _ in _lib.ServerJobStats._fields_}
+        check(status)
+        return UBLR(h, plan, prec, r_lo), stats
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().blr_server_destroy(h)
+            self._h = None
+        self._pending = {}
+
+    def __del__(self):
+        self.close()
 
 
 def compress(plan: Plan, op: Operator, G, H, keep_intermediates: bool = False, report: bool = True,

@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <tuple>
+#include <mutex>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -948,4 +952,434 @@ blr_status blr_error_power(const blr_ublr* h, const blr_operator* op, const doub
     });
 }
 
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+// Bytes of one compression (outputs and temporaries), by the allocation plan of
+// blr_tag_compress and of the batch.
+int64_t footprint_bytes(const PlanData& P, int precision, int r_lo) {
+    const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+    int64_t d = 2 * P.n * P.k + bk * bk + P.b_values + nearfield_workspace_doubles(P);
+    int64_t bytes = 0;
+    if (is_mixed(precision)) {
+        const int64_t LR = static_cast<int64_t>(P.ell) * r_lo;
+        const int64_t esize = precision == BLR_PREC_BF16_REFINE ? 2 : 4;
+        bytes += 2 * P.n * LR * 4 + 2 * lp_packed_elems(P, r_lo) * esize;
+        d += 4 * P.n * r_lo + 4 * P.n * P.r;
+    } else {
+        d += 2 * P.n * static_cast<int64_t>(P.ell) * P.r + 2 * P.n * P.r;
+    }
+    return bytes + d * static_cast<int64_t>(sizeof(double));
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tuned_spw;  // (device, precision, ntr) -> SPW
+
+}  // namespace
+
+blr_status blr_plan_footprint(const blr_plan* plan, int32_t precision, int32_t r_lo, int64_t* bytes) {
+    return guard([&] {
+        const PlanData& P = plan_of(plan);
+        if (!bytes) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        if (!is_mixed(precision) && precision != BLR_PREC_FP64) fail(BLR_ERR_UNSUPPORTED, "unsupported precision");
+        const int rl = is_mixed(precision) ? (r_lo ? r_lo : P.r) : P.r;
+        if (is_mixed(precision)) check_r_lo(P, rl);
+        *bytes = footprint_bytes(P, precision, rl);
+    });
+}
+
+}  // extern "C"
+
+namespace blr {
+namespace {
+
+struct BatchJob {
+    std::shared_ptr<PlanData> plan;
+    const OpData* op = nullptr;
+    const double* G = nullptr;
+    const double* H = nullptr;
+    int precision = BLR_PREC_FP64;
+    int r_lo = 0;
+    const double* gamma_u = nullptr;
+    const double* gamma_v = nullptr;
+    blr_ublr* handle = nullptr;
+    const DeviceTables* t = nullptr;
+    bool persistent = false;  // sketch in a persistent class launch
+    double *Y = nullptr, *Z = nullptr;
+    float *Y0 = nullptr, *Z0 = nullptr;
+    void *PG = nullptr, *PH = nullptr;
+    double *Yh = nullptr, *Zh = nullptr, *U0 = nullptr, *V0 = nullptr;
+    double *Xv = nullptr, *Xu = nullptr, *SY = nullptr, *SZ = nullptr, *nfw = nullptr;
+};
+
+struct SketchClass {
+    int precision = 0, ntr = 0;
+    std::vector<int> members;
+    LpJob* d_jobs = nullptr;
+    int nspw = 0;
+    int spw[2] = {0, 0};
+    int4* d_items[2] = {nullptr, nullptr};
+    int nitems[2] = {0, 0};
+    int chosen = 0;
+};
+
+}  // namespace
+}  // namespace blr
+
+struct blr_batch {
+    std::vector<blr::BatchJob> jobs;
+    std::vector<blr::SketchClass> classes;
+    std::vector<void*> mem;
+    int device = -1;
+    int flags = 0;
+    int runs = 0;
+    int grid = 512;
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~blr_batch() {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (device >= 0) (void)hipSetDevice(device);
+        if (own) (void)hipStreamSynchronize(own);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto& j : jobs) delete j.handle;
+        for (void* p : mem) (void)hipFree(p);
+        for (hipEvent_t e : {ev_in, ev_out, e0, e1, e2})
+            if (e) (void)hipEventDestroy(e);
+        if (own) (void)hipStreamDestroy(own);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+    template <class T>
+    T* alloc(int64_t count) {
+        void* p = nullptr;
+        const size_t bytes = static_cast<size_t>(std::max<int64_t>(1, count)) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            blr::fail(BLR_ERR_OOM, "device allocation for the batch failed");
+        }
+        mem.push_back(p);
+        return static_cast<T*>(p);
+    }
+};
+
+namespace blr {
+namespace {
+
+void batch_enqueue(blr_batch& B, bool time_sketch) {
+    hipStream_t s = B.own;
+    for (auto& j : B.jobs) {
+        const PlanData& P = *j.plan;
+        if (is_mixed(j.precision)) {
+            launch_pack_lp(P, *j.t, j.precision, j.r_lo, j.G, j.PG, s);
+            launch_pack_lp(P, *j.t, j.precision, j.r_lo, j.H, j.PH, s);
+            if (!j.persistent) launch_sketch_lp(*j.op, P, *j.t, j.precision, j.r_lo, j.PG, j.PH, j.Y0, j.Z0, s);
+        } else {
+            launch_sketch(*j.op, P, *j.t, j.G, j.H, j.Y, j.Z, s);
+        }
+    }
+    if (time_sketch) HIPC(hipEventRecord(B.e0, s));
+    for (auto& c : B.classes)
+        launch_sketch_lp_multi(c.precision, c.ntr, c.spw[c.chosen], c.d_jobs, c.d_items[c.chosen],
+                               c.nitems[c.chosen], B.grid, s);
+    if (time_sketch) HIPC(hipEventRecord(B.e1, s));
+    for (auto& j : B.jobs) {
+        const PlanData& P = *j.plan;
+        const DeviceTables& t = *j.t;
+        UblrData& h = *j.handle->d;
+        if (is_mixed(j.precision)) {
+            launch_postprocess_lp(P, t, j.r_lo, j.Y0, j.Yh, s);
+            launch_postprocess_lp(P, t, j.r_lo, j.Z0, j.Zh, s);
+            launch_orth_cols(P, t, j.r_lo, j.r_lo, 1, j.Yh, j.Zh, j.U0, j.V0, nullptr, nullptr, s);
+            launch_mix(P, t, j.r_lo, j.V0, j.gamma_v, j.Xv, s);
+            launch_mix(P, t, j.r_lo, j.U0, j.gamma_u, j.Xu, s);
+            launch_refine(*j.op, P, t, j.Xv, j.Xu, j.SY, j.SZ, s);
+            launch_orth2(P, t, j.SY, j.SZ, h.U, h.V, nullptr, nullptr, s);
+        } else {
+            launch_postprocess(P, t, j.Y, j.Yh, s);
+            launch_postprocess(P, t, j.Z, j.Zh, s);
+            launch_orth2(P, t, j.Yh, j.Zh, h.U, h.V, nullptr, nullptr, s);
+        }
+        launch_cores(*j.op, P, t, h.U, h.V, h.Atil, s);
+        launch_nearfield(*j.op, P, t, h.U, h.V, h.Atil, h.B, j.nfw, s);
+    }
+}
+
+// Times every SPW candidate of each class on the real items and keeps the fastest
+// (the persistent sketch's results do not depend on SPW: each tag column's sums
+// run in the same order).
+void batch_autotune(blr_batch& B) {
+    hipStream_t s = B.own;
+    for (auto& c : B.classes) {
+        const auto key = std::make_tuple(B.device, c.precision, c.ntr);
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tuned_spw.find(key);
+            if (it != g_tuned_spw.end()) {
+                for (int q = 0; q < c.nspw; ++q)
+                    if (c.spw[q] == it->second) c.chosen = q;
+                continue;
+            }
+        }
+        float best = 0.0f;
+        int bq = 0;
+        for (int q = 0; q < c.nspw; ++q) {
+            HIPC(hipEventRecord(B.e0, s));
+            launch_sketch_lp_multi(c.precision, c.ntr, c.spw[q], c.d_jobs, c.d_items[q], c.nitems[q], B.grid, s);
+            HIPC(hipEventRecord(B.e1, s));
+            HIPC(hipEventSynchronize(B.e1));
+            float ms = 0.0f;
+            HIPC(hipEventElapsedTime(&ms, B.e0, B.e1));
+            if (q == 0 || ms < best) {
+                best = ms;
+                bq = q;
+            }
+        }
+        c.chosen = bq;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned_spw[key] = c.spw[bq];
+    }
+}
+
+}  // namespace
+}  // namespace blr
+
+extern "C" {
+
+blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t flags, blr_batch** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out || !jobs) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (njobs < 1) fail(BLR_ERR_INVALID_ARG, "njobs must be positive");
+        auto B = std::make_unique<blr_batch>();
+        B->device = current_device();
+        B->flags = flags;
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device);
+        B->grid = 2 * std::max(1, cus);
+        B->jobs.resize(njobs);
+        for (int q = 0; q < njobs; ++q) {
+            const blr_batch_job& in = jobs[q];
+            BatchJob& j = B->jobs[q];
+            const PlanData& P = plan_of(in.plan);
+            const OpData& o = op_of(in.op, P);
+            if (is_callback(o)) fail(BLR_ERR_UNSUPPORTED, "batches need built-in operators");
+            if (!in.G || !in.H) fail(BLR_ERR_INVALID_ARG, "NULL G or H");
+            if (in.opts.reserved != 0) fail(BLR_ERR_INVALID_ARG, "reserved option field must be 0");
+            j.plan = in.plan->d;
+            j.op = &o;
+            j.G = in.G;
+            j.H = in.H;
+            j.precision = in.opts.precision;
+            if (!is_mixed(j.precision) && j.precision != BLR_PREC_FP64) fail(BLR_ERR_UNSUPPORTED, "unsupported precision");
+            j.r_lo = is_mixed(j.precision) ? (in.opts.r_lo ? in.opts.r_lo : P.r) : P.r;
+            if (is_mixed(j.precision)) {
+                check_r_lo(P, j.r_lo);
+                if (!in.opts.gamma_u || !in.opts.gamma_v) fail(BLR_ERR_INVALID_ARG, "mixed modes need gamma_u and gamma_v");
+            }
+            j.gamma_u = in.opts.gamma_u;
+            j.gamma_v = in.opts.gamma_v;
+            j.t = &j.plan->tables();
+            // outputs
+            auto h = std::make_unique<UblrData>();
+            h->plan = j.plan;
+            h->device = B->device;
+            h->precision = j.precision;
+            h->r_lo = j.r_lo;
+            const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+            h->U = dalloc_sync(P.n * P.k);
+            h->V = dalloc_sync(P.n * P.k);
+            h->Atil = dalloc_sync(bk * bk);
+            h->B = dalloc_sync(P.b_values);
+            j.handle = new blr_ublr;
+            j.handle->d = std::move(h);
+            // temporaries
+            const int64_t LR = static_cast<int64_t>(P.ell) * j.r_lo;
+            if (is_mixed(j.precision)) {
+                const int64_t esize = j.precision == BLR_PREC_BF16_REFINE ? 2 : 4;
+                j.Y0 = B->alloc<float>(P.n * LR);
+                j.Z0 = B->alloc<float>(P.n * LR);
+                j.PG = B->alloc<char>(lp_packed_elems(P, j.r_lo) * esize);
+                j.PH = B->alloc<char>(lp_packed_elems(P, j.r_lo) * esize);
+                j.U0 = B->alloc<double>(P.n * j.r_lo);
+                j.V0 = B->alloc<double>(P.n * j.r_lo);
+                j.Xv = B->alloc<double>(P.n * P.r);
+                j.Xu = B->alloc<double>(P.n * P.r);
+                j.SY = B->alloc<double>(P.n * P.r);
+                j.SZ = B->alloc<double>(P.n * P.r);
+                j.persistent = o.type == OpType::Kernel;
+            } else {
+                j.Y = B->alloc<double>(P.n * LR);
+                j.Z = B->alloc<double>(P.n * LR);
+            }
+            j.Yh = B->alloc<double>(P.n * j.r_lo);
+            j.Zh = B->alloc<double>(P.n * j.r_lo);
+            j.nfw = B->alloc<double>(nearfield_workspace_doubles(P));
+        }
+        // persistent sketch classes: (precision, column tiles)
+        for (int q = 0; q < njobs; ++q) {
+            BatchJob& j = B->jobs[q];
+            if (!j.persistent) continue;
+            const int ntr = (j.r_lo + 15) / 16;
+            SketchClass* c = nullptr;
+            for (auto& x : B->classes)
+                if (x.precision == j.precision && x.ntr == ntr) c = &x;
+            if (!c) {
+                if (B->classes.size() >= 8) fail(BLR_ERR_UNSUPPORTED, "more than 8 sketch classes");
+                B->classes.emplace_back();
+                c = &B->classes.back();
+                c->precision = j.precision;
+                c->ntr = ntr;
+            }
+            c->members.push_back(q);
+        }
+        for (auto& c : B->classes) {
+            std::vector<LpJob> lj;
+            for (int q : c.members) {
+                const BatchJob& j = B->jobs[q];
+                const PlanData& P = *j.plan;
+                LpJob d{};
+                d.kind = j.op->kind;
+                d.diag = j.op->kind == BLR_KERNEL_EXP ? 1.0f : (j.op->kind == BLR_KERNEL_COS ? 1000.0f : 0.0f);
+                d.px = j.op->pts32;
+                d.py = j.op->pts32 + P.n;
+                d.pz = j.op->pts32 + 2 * P.n;
+                d.Tf = j.t->Tf;
+                d.box_ptr = j.t->box_ptr;
+                d.nbox = P.b;
+                d.r = j.r_lo;
+                d.ell = P.ell;
+                d.n = P.n;
+                d.B0 = j.PG;
+                d.B1 = j.PH;
+                d.Y0 = j.Y0;
+                d.Y1 = j.Z0;
+                lj.push_back(d);
+            }
+            c.d_jobs = B->alloc<LpJob>(static_cast<int64_t>(lj.size()));
+            HIPC(hipMemcpy(c.d_jobs, lj.data(), lj.size() * sizeof(LpJob), hipMemcpyHostToDevice));
+            c.nspw = lp_multi_spw_candidates(c.precision, c.ntr, c.spw);
+            for (int v = 0; v < c.nspw; ++v) {
+                // items: (job index in class, 32-row block, tag column group), heaviest job first
+                std::vector<std::pair<double, int4>> items;
+                for (size_t u = 0; u < c.members.size(); ++u) {
+                    const PlanData& P = *B->jobs[c.members[u]].plan;
+                    const int groups = (P.ell + 2 * c.spw[v] - 1) / (2 * c.spw[v]);
+                    const int64_t blocks = (P.n + 31) / 32;
+                    if (blocks > INT32_MAX) fail(BLR_ERR_UNSUPPORTED, "job too large for the batch");
+                    const double cost = static_cast<double>(P.n) * P.ell;
+                    for (int64_t rb = 0; rb < blocks; ++rb)
+                        for (int g = 0; g < groups; ++g)
+                            items.push_back({cost, int4{static_cast<int>(u), static_cast<int>(rb), g, 0}});
+                }
+                std::stable_sort(items.begin(), items.end(),
+                                 [](const auto& a, const auto& b) { return a.first > b.first; });
+                std::vector<int4> flat(items.size());
+                for (size_t u = 0; u < items.size(); ++u) flat[u] = items[u].second;
+                c.d_items[v] = B->alloc<int4>(static_cast<int64_t>(flat.size()));
+                HIPC(hipMemcpy(c.d_items[v], flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice));
+                c.nitems[v] = static_cast<int>(flat.size());
+            }
+        }
+        HIPC(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
+        for (hipEvent_t* e : {&B->ev_in, &B->ev_out, &B->e0, &B->e1, &B->e2}) HIPC(hipEventCreate(e));
+        *out = B.release();
+    });
+}
+
+blr_status blr_batch_run(blr_batch* b, void* stream, blr_batch_report* rep) {
+    return guard([&] {
+        if (!b) fail(BLR_ERR_INVALID_ARG, "NULL batch");
+        if (b->device != current_device()) fail(BLR_ERR_INVALID_ARG, "batch belongs to another device");
+        hipStream_t us = static_cast<hipStream_t>(stream);
+        HIPC(hipEventRecord(b->ev_in, us));
+        HIPC(hipStreamWaitEvent(b->own, b->ev_in, 0));
+        const bool first = b->runs == 0;
+        bool replayed = false;
+        if (b->exec) {
+            HIPC(hipEventRecord(b->e0, b->own));
+            HIPC(hipGraphLaunch(b->exec, b->own));
+            HIPC(hipEventRecord(b->e2, b->own));
+            replayed = true;
+        } else if ((b->flags & BLR_BATCH_GRAPH) && !first) {
+            HIPC(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+            try {
+                batch_enqueue(*b, false);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(b->own, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIPC(hipStreamEndCapture(b->own, &b->graph));
+            HIPC(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            HIPC(hipEventRecord(b->e0, b->own));
+            HIPC(hipGraphLaunch(b->exec, b->own));
+            HIPC(hipEventRecord(b->e2, b->own));
+            replayed = true;
+        } else {
+            hipEvent_t start;
+            HIPC(hipEventCreate(&start));
+            HIPC(hipEventRecord(start, b->own));
+            batch_enqueue(*b, true);
+            HIPC(hipEventRecord(b->e2, b->own));
+            if (rep) {
+                HIPC(hipEventSynchronize(b->e2));
+                float tot = 0.0f, sk = 0.0f;
+                HIPC(hipEventElapsedTime(&tot, start, b->e2));
+                HIPC(hipEventElapsedTime(&sk, b->e0, b->e1));
+                std::memset(rep, 0, sizeof(*rep));
+                rep->ms_total = tot;
+                rep->ms_sketch = sk;
+            }
+            (void)hipEventDestroy(start);
+            // after the first eager run (inputs packed): time the SPW candidates of each
+            // persistent class on the real items; later runs use the fastest
+            if (first && (b->flags & BLR_BATCH_AUTOTUNE)) batch_autotune(*b);
+        }
+        HIPC(hipEventRecord(b->ev_out, b->own));
+        HIPC(hipStreamWaitEvent(us, b->ev_out, 0));
+        ++b->runs;
+        if (rep) {
+            if (replayed) {
+                HIPC(hipEventSynchronize(b->e2));
+                float tot = 0.0f;
+                HIPC(hipEventElapsedTime(&tot, b->e0, b->e2));
+                std::memset(rep, 0, sizeof(*rep));
+                rep->ms_total = tot;
+                rep->graph_replayed = 1;
+            }
+            for (const auto& j : b->jobs) {
+                const PlanData& P = *j.plan;
+                const int64_t LR = static_cast<int64_t>(P.ell) * j.r_lo;
+                const bool mixed = is_mixed(j.precision);
+                rep->sketch_flops += 4.0 * static_cast<double>(P.n) * static_cast<double>(P.n) * static_cast<double>(LR);
+                if (mixed) rep->refine_flops += refine_flops(P);
+                const int64_t rc = mixed ? static_cast<int64_t>(P.b) * P.r : 0;
+                rep->applies += 2 * (LR + rc) + static_cast<int64_t>(P.b) * P.k + static_cast<int64_t>(P.ncol) * P.m_max;
+            }
+            rep->nclasses = static_cast<int32_t>(b->classes.size());
+            for (size_t q = 0; q < b->classes.size(); ++q) {
+                rep->class_precision[q] = b->classes[q].precision;
+                rep->class_ntr[q] = b->classes[q].ntr;
+                rep->class_spw[q] = b->classes[q].spw[b->classes[q].chosen];
+                rep->class_jobs[q] = static_cast<int32_t>(b->classes[q].members.size());
+            }
+        }
+    });
+}
+
+blr_status blr_batch_result(const blr_batch* b, int32_t job, const blr_ublr** h) {
+    if (h) *h = nullptr;
+    return guard([&] {
+        if (!b || !h) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (job < 0 || job >= static_cast<int32_t>(b->jobs.size())) fail(BLR_ERR_INVALID_ARG, "job out of range");
+        *h = b->jobs[job].handle;
+    });
+}
+
+void blr_batch_destroy(blr_batch* b) { delete b; }
 }  // extern "C"

@@ -12,6 +12,8 @@
 //   D (16x16): lane l, element v holds D[l / 16 + 4*v][l % 16]
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <sstream>
@@ -1606,9 +1608,19 @@ void launch_orth_cols(const PlanData& P, const DeviceTables& t, int r, int k, in
     const int m_in_lds = (small + big <= lds_limit) ? 1 : 0;
     const size_t dyn = small + (m_in_lds ? big : 0);
     if (dyn > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_orth),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
-        if (e != hipSuccess) fail(BLR_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
+        // raise the kernel's dynamic LDS limit once per device and size (not during a
+        // stream capture that follows an eager run of the same shapes)
+        static std::mutex mu;
+        static size_t set_bytes[64] = {};
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lock(mu);
+        if (dev < 0 || dev >= 64 || dyn > set_bytes[dev]) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_orth),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+            if (e != hipSuccess) fail(BLR_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
+            if (dev >= 0 && dev < 64) set_bytes[dev] = dyn;
+        }
     }
     const int nsides = S1 ? 2 : 1;
     hipLaunchKernelGGL(k_orth, dim3(nsides * P.b), dim3(256), dyn, s, S0, S1 ? S1 : S0, P.n, t.box_ptr,

@@ -35,6 +35,32 @@ void launch_orth2(const PlanData& P, const DeviceTables& t, double* S0, double* 
 void launch_cores(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
                   const double* V, double* Atil, hipStream_t s);
 
+// One kernel-matrix job of a persistent low-precision sketch launch (device array).
+struct LpJob {
+    int kind;                 // blr_kernel_kind
+    float diag;               // kernel diagonal value
+    const float* px;          // FP32 points, SoA
+    const float* py;
+    const float* pz;
+    const float* Tf;          // b x ell row-major, FP32
+    const int64_t* box_ptr;   // [b+1]
+    int nbox;
+    int r;                    // r_lo
+    int ell;
+    int64_t n;
+    const void* B0;           // packed G (lp_packed_elems of the precision's type)
+    const void* B1;           // packed H
+    float* Y0;                // N x ell r_lo
+    float* Y1;
+};
+// Tag columns per wave (SPW) offered to the autotuner for a (precision, column
+// tiles) class; a workgroup covers 2 SPW tag columns.  Returns the count (<= 2).
+int lp_multi_spw_candidates(int precision, int ntr, int* spw);
+// Persistent sketch over items (job, 32-row block, tag column group) built for the
+// given SPW; grid workgroups stride over the items.
+void launch_sketch_lp_multi(int precision, int ntr, int spw, const LpJob* jobs, const int4* items,
+                            int nitems, int grid, hipStream_t s);
+
 // Mixed-precision mode (kernels_lp.hip): [G|H] packed per side into MFMA
 // fragment order (lp_packed_elems elements of 2 bytes for BF16, 4 for FP32),
 // the low-precision tagged sketch into FP32 Y, Z (N x ell r_lo), and the mixing

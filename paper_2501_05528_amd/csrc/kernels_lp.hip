@@ -154,27 +154,38 @@ __global__ __launch_bounds__(256) void k_pack_lp(const double* __restrict__ G, i
 //   16x16x4 F32 (8 of them per step, number e): A lane L: A[L % 16][8 (L / 16) + e],
 //                  B lane L: B[8 (L / 16) + e][L % 16]  (the same K assignment);
 //   D lane L, element v: D[4 (L / 16) + v][L % 16] for both.
-template <class AS, int PREC, int NTR, int NSIDE, int SPW>
-__global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restrict__ Tf,
-                                                      const int64_t* __restrict__ box_ptr, int nbox,
-                                                      const typename LpElem<PREC>::T* __restrict__ B0,
-                                                      const typename LpElem<PREC>::T* __restrict__ B1,
-                                                      int64_t n, int r, int ell,
-                                                      float* __restrict__ Y0, float* __restrict__ Y1) {
+template <int PREC, int NTR, int NSIDE>
+struct LpTile {
     using E = typename LpElem<PREC>::T;
-    constexpr int BM = 32, KT = LP_KT, AST = KT + 4;           // rows, sources/step, LDS row stride
-    constexpr int FRAG = 64 * 8;                               // elements of one B fragment
-    constexpr int BEL = NSIDE * NTR * FRAG;                    // B elements per step
+    static constexpr int BM = 32, KT = LP_KT, AST = KT + 4;    // rows, sources/step, LDS row stride
+    static constexpr int FRAG = 64 * 8;                        // elements of one B fragment
+    static constexpr int BEL = NSIDE * NTR * FRAG;             // B elements per step
+};
+
+// One workgroup tile of the sketch: target rows [32 rt_blk, 32 rt_blk + 32) and tag
+// column group grp.  sAp / sBp: double-buffered LDS tiles (2 x BM*AST floats, 2 x BEL
+// elements), 16-byte aligned.
+template <class AS, int PREC, int NTR, int NSIDE, int SPW>
+__device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
+                                      const int64_t* __restrict__ box_ptr, int nbox,
+                                      const typename LpElem<PREC>::T* __restrict__ B0,
+                                      const typename LpElem<PREC>::T* __restrict__ B1, int64_t n,
+                                      int r, int ell, float* __restrict__ Y0, float* __restrict__ Y1,
+                                      int64_t rt_blk, int grp, float* sAp,
+                                      typename LpElem<PREC>::T* sBp) {
+    using E = typename LpElem<PREC>::T;
+    using TL = LpTile<PREC, NTR, NSIDE>;
+    constexpr int BM = TL::BM, KT = TL::KT, AST = TL::AST, FRAG = TL::FRAG, BEL = TL::BEL;
     constexpr int CH_EL = 16 / sizeof(E);                      // elements per 16-byte chunk
     constexpr int NCH = BEL / CH_EL;                           // 16-byte chunks per step
     constexpr int CPT = (NCH + 255) / 256;                     // chunks per thread
-    __shared__ __attribute__((aligned(16))) float sA[2][BM * AST];
-    __shared__ __attribute__((aligned(16))) E sB[2][BEL];
+    float (*sA)[BM * AST] = reinterpret_cast<float (*)[BM * AST]>(sAp);
+    E (*sB)[BEL] = reinterpret_cast<E (*)[BEL]>(sBp);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rt = wave & 1, half = wave >> 1;
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
-    const int sg0 = blockIdx.y * 2 * SPW;
+    const int64_t row0 = rt_blk * BM;
+    const int sg0 = grp * 2 * SPW;
     const int sgn = min(2 * SPW, ell - sg0);
     const int s_lo = sg0 + (half * sgn) / 2;
     const int nsv = sg0 + ((half + 1) * sgn) / 2 - s_lo;
@@ -351,6 +362,63 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
     }
 }
 
+template <class AS, int PREC, int NTR, int NSIDE, int SPW>
+__global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restrict__ Tf,
+                                                      const int64_t* __restrict__ box_ptr, int nbox,
+                                                      const typename LpElem<PREC>::T* __restrict__ B0,
+                                                      const typename LpElem<PREC>::T* __restrict__ B1,
+                                                      int64_t n, int r, int ell,
+                                                      float* __restrict__ Y0, float* __restrict__ Y1) {
+    using TL = LpTile<PREC, NTR, NSIDE>;
+    __shared__ __attribute__((aligned(16))) float sA[2 * TL::BM * TL::AST];
+    __shared__ __attribute__((aligned(16))) typename TL::E sB[2 * TL::BEL];
+    sketch_lp_tile<AS, PREC, NTR, NSIDE, SPW>(A, Tf, box_ptr, nbox, B0, B1, n, r, ell, Y0, Y1,
+                                              blockIdx.x, blockIdx.y, sA, sB);
+}
+
+// Persistent form over a batch of kernel-matrix jobs: workgroups stride over a
+// list of (job, row block, tag column group) items, heaviest first; the kernel
+// kind of each job is dispatched per item.
+template <int PREC, int NTR, int SPW>
+__global__ __launch_bounds__(256, 2) void k_sketch_lp_multi(const LpJob* __restrict__ jobs,
+                                                            const int4* __restrict__ items,
+                                                            int nitems) {
+    using TL = LpTile<PREC, NTR, 2>;
+    using E = typename TL::E;
+    __shared__ __attribute__((aligned(16))) float sA[2 * TL::BM * TL::AST];
+    __shared__ __attribute__((aligned(16))) E sB[2 * TL::BEL];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        const LpJob& J = jobs[w.x];
+        const int64_t rt_blk = static_cast<int64_t>(w.y);
+        const E* b0 = static_cast<const E*>(J.B0);
+        const E* b1 = static_cast<const E*>(J.B1);
+        __syncthreads();  // the previous item's last reads of LDS are done
+        switch (J.kind) {
+            case BLR_KERNEL_LOG:
+                sketch_lp_tile<KernelSrc32<BLR_KERNEL_LOG>, PREC, NTR, 2, SPW>(
+                    KernelSrc32<BLR_KERNEL_LOG>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                break;
+            case BLR_KERNEL_INV_R:
+                sketch_lp_tile<KernelSrc32<BLR_KERNEL_INV_R>, PREC, NTR, 2, SPW>(
+                    KernelSrc32<BLR_KERNEL_INV_R>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                break;
+            case BLR_KERNEL_EXP:
+                sketch_lp_tile<KernelSrc32<BLR_KERNEL_EXP>, PREC, NTR, 2, SPW>(
+                    KernelSrc32<BLR_KERNEL_EXP>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                break;
+            default:
+                sketch_lp_tile<KernelSrc32<BLR_KERNEL_COS>, PREC, NTR, 2, SPW>(
+                    KernelSrc32<BLR_KERNEL_COS>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                break;
+        }
+    }
+}
+
 template <int PREC, class AS>
 void sketch_lp_launch(AS A, const PlanData& P, const DeviceTables& t, int r, const void* B0,
                       const void* B1, int nside, float* Y0, float* Y1, hipStream_t s) {
@@ -474,6 +542,40 @@ void launch_sketch_lp(const OpData& op, const PlanData& P, const DeviceTables& t
         run(std::integral_constant<int, BLR_PREC_FP32_REFINE>{});
     else
         fail(BLR_ERR_INVALID_ARG, "not a low-precision mode");
+}
+
+int lp_multi_spw_candidates(int precision, int ntr, int* spw) {
+    static const int bf16[6][2] = {{0, 0}, {8, 4}, {8, 4}, {7, 4}, {5, 3}, {4, 2}};
+    static const int fp32[6][2] = {{0, 0}, {8, 4}, {7, 4}, {5, 3}, {3, 2}, {3, 2}};
+    if (ntr < 1 || ntr > 5) fail(BLR_ERR_UNSUPPORTED, "r_lo > 80 is not supported by the low-precision sketch");
+    const int(*tab)[2] = precision == BLR_PREC_BF16_REFINE ? bf16 : fp32;
+    spw[0] = tab[ntr][0];
+    spw[1] = tab[ntr][1];
+    return 2;
+}
+
+void launch_sketch_lp_multi(int precision, int ntr, int spw, const LpJob* jobs, const int4* items,
+                            int nitems, int grid, hipStream_t s) {
+    if (nitems <= 0) return;
+    const dim3 g(static_cast<unsigned>(std::max(1, std::min(grid, nitems))));
+#define BLR_LPM(PRECV, NTRV, SPWV)                                                                 \
+    if (precision == PRECV && ntr == NTRV && spw == SPWV) {                                        \
+        hipLaunchKernelGGL((k_sketch_lp_multi<PRECV, NTRV, SPWV>), g, dim3(256), 0, s, jobs, items, nitems); \
+        check_launch_lp("persistent low-precision sketch");                                        \
+        return;                                                                                    \
+    }
+    BLR_LPM(BLR_PREC_BF16_REFINE, 1, 8) BLR_LPM(BLR_PREC_BF16_REFINE, 1, 4)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 2, 8) BLR_LPM(BLR_PREC_BF16_REFINE, 2, 4)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 3, 7) BLR_LPM(BLR_PREC_BF16_REFINE, 3, 4)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 4, 5) BLR_LPM(BLR_PREC_BF16_REFINE, 4, 3)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 5, 4) BLR_LPM(BLR_PREC_BF16_REFINE, 5, 2)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 1, 8) BLR_LPM(BLR_PREC_FP32_REFINE, 1, 4)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 2, 7) BLR_LPM(BLR_PREC_FP32_REFINE, 2, 4)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 3, 5) BLR_LPM(BLR_PREC_FP32_REFINE, 3, 3)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 4, 3) BLR_LPM(BLR_PREC_FP32_REFINE, 4, 2)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 5, 3) BLR_LPM(BLR_PREC_FP32_REFINE, 5, 2)
+#undef BLR_LPM
+    fail(BLR_ERR_INVALID_ARG, "no persistent sketch for this precision, column tiles and SPW");
 }
 
 void launch_mix(const PlanData& P, const DeviceTables& t, int r_lo, const double* Q0,

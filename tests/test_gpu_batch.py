@@ -1,0 +1,136 @@
+"""GPU tests of batched compression (blr_batch_*): uneven jobs from the batch generator
+(N, box size, rank and kernel drawn per job), mixed BF16 / FP32 and FP64 jobs, a dense
+operator among them.
+
+* Every job's U, V, Atil, B from the batch equal those of blr_tag_compress on the same
+  inputs, bit for bit, on the eager first run, on the run that captures the HIP graph and
+  on later replays (with unrelated eager work on the stream between replays).
+* The autotuner picks one of the offered tile shapes per persistent sketch class.
+* A sampled job's error meets the 1.5 band of the FP64 oracle's plain tagging.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SPW_CANDIDATES = {2: {1: (8, 4), 2: (8, 4), 3: (7, 4), 4: (5, 3), 5: (4, 2)},
+                  1: {1: (8, 4), 2: (7, 4), 3: (5, 3), 4: (3, 2), 5: (3, 2)}}
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    import torch
+    import paper_2501_05528_amd as P
+    jobs = W.uneven_batch_jobs(9, 20250104, n_lo=2048, n_hi=12288)
+    precs = ["bf16", "fp32", "fp64"]
+    specs = []
+    for q, wl in enumerate(jobs):
+        g = wl.geometry()
+        near = O.near_lists(g.lattice)
+        T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, 3))
+        prec = precs[q % 3]
+        r = wl.k + wl.p
+        G, H = W.gaussian_test_blocks(wl.seed, g.n, r)
+        gu, gv = W.refinement_gammas(wl.seed, g.nboxes, r, r)
+        plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=3)
+        op = P.Operator.kernel(wl.kind, g.pts)
+        specs.append(dict(wl=wl, g=g, T=T, plan=plan, op=op, G=P.colmajor(G), H=P.colmajor(H),
+                          gamma_u=torch.as_tensor(gu, device="cuda"), gamma_v=torch.as_tensor(gv, device="cuda"),
+                          precision=prec))
+    # a dense operator in mixed mode (single-job sketch inside the batch)
+    wl = W.WORKLOADS["planted_2d_n4096"]
+    g = wl.geometry()
+    A, _, _ = W.planted_exact_rank(g, wl.k, wl.seed)
+    near = O.near_lists(g.lattice)
+    T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, 3))
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    gu, gv = W.refinement_gammas(wl.seed, g.nboxes, wl.r, wl.r)
+    Ad = P.colmajor(A)
+    specs.append(dict(wl=wl, g=g, T=T, plan=P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=3),
+                      op=P.Operator.dense(Ad), A=Ad, G=P.colmajor(G), H=P.colmajor(H),
+                      gamma_u=torch.as_tensor(gu, device="cuda"), gamma_v=torch.as_tensor(gv, device="cuda"),
+                      precision="bf16"))
+    for q, sp in enumerate(specs):
+        _announce(f"batch job {q}: N={sp['g'].n} b={sp['g'].nboxes} k={sp['wl'].k} "
+                  f"kind={sp['wl'].kind} {sp['precision']}")
+    singles = []
+    for sp in specs:
+        kw = {} if sp["precision"] == "fp64" else dict(precision=sp["precision"], gamma_u=sp["gamma_u"],
+                                                        gamma_v=sp["gamma_v"])
+        h, _ = P.compress(sp["plan"], sp["op"], sp["G"], sp["H"], **kw)
+        singles.append({x: h.part(x) for x in ("U", "V", "Atil", "B")})
+    torch.cuda.synchronize()
+    return dict(P=P, specs=specs, singles=singles)
+
+
+def _check_equal(batch, singles):
+    for q, ref in enumerate(singles):
+        h = batch.result(q)
+        for x in ("U", "V", "Atil", "B"):
+            got = h.part(x)
+            assert (got == ref[x]).all().item(), (q, x)
+
+
+def test_batch_equals_single_jobs_eager_and_graph(batch_setup):
+    import torch
+    P, specs, singles = batch_setup["P"], batch_setup["specs"], batch_setup["singles"]
+    jobs = [dict(plan=s["plan"], op=s["op"], G=s["G"], H=s["H"], precision=s["precision"],
+                 gamma_u=s["gamma_u"], gamma_v=s["gamma_v"]) for s in specs]
+    b = P.Batch(jobs, graph=True, autotune=True)
+    rep1 = b.run()
+    torch.cuda.synchronize()
+    _announce(f"batch eager run: {rep1['ms_total']:.2f} ms, classes ntr={rep1['class_ntr']} "
+              f"spw={rep1['class_spw']} jobs={rep1['class_jobs']}")
+    assert rep1["graph_replayed"] == 0 and rep1["nclasses"] >= 1
+    _check_equal(b, singles)
+    rep2 = b.run()            # captures and launches the graph
+    torch.cuda.synchronize()
+    assert rep2["graph_replayed"] == 1
+    _check_equal(b, singles)
+    for _ in range(2):        # replays with unrelated eager work in between
+        sp = specs[0]
+        P.compress(sp["plan"], sp["op"], sp["G"], sp["H"], precision=sp["precision"],
+                   gamma_u=sp["gamma_u"], gamma_v=sp["gamma_v"])
+        rep = b.run()
+        torch.cuda.synchronize()
+        assert rep["graph_replayed"] == 1
+        _check_equal(b, singles)
+    for prec, ntr, spw in zip(rep2["class_precision"], rep2["class_ntr"], rep2["class_spw"]):
+        assert spw in SPW_CANDIDATES[prec][ntr]
+    assert rep2["sketch_flops"] > 0 and rep2["applies"] > 0
+
+
+def test_batch_job_error_band(batch_setup):
+    import torch
+    P, specs = batch_setup["P"], batch_setup["specs"]
+    jobs = [dict(plan=s["plan"], op=s["op"], G=s["G"], H=s["H"], precision=s["precision"],
+                 gamma_u=s["gamma_u"], gamma_v=s["gamma_v"]) for s in specs]
+    b = P.Batch(jobs, graph=False, autotune=False)
+    b.run()
+    torch.cuda.synchronize()
+    q = min(range(len(specs) - 1), key=lambda i: specs[i]["g"].n)   # smallest kernel job
+    sp = specs[q]
+    g, wl = sp["g"], sp["wl"]
+    A = O.KernelOperator(wl.kind, g.pts).block()
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, wl.k, wl.p, 3, sp["T"], G, H)
+    e_or = O.rel_fro_error(O.DenseOperator(A), res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, wl.k)
+    e = b.result(q).error_fro(sp["op"])
+    _announce(f"batch job {q} ({sp['precision']}): rel fro error {e:.3e}, oracle {e_or:.3e}")
+    assert e <= 1.5 * e_or + 1e-12
+
+
+def test_footprint(batch_setup):
+    P, specs = batch_setup["P"], batch_setup["specs"]
+    for sp in specs:
+        plan = sp["plan"]
+        out_bytes = 8 * (2 * plan.n * plan.k + (plan.b * plan.k) ** 2 + plan.info["b_values"])
+        for prec in ("fp64", "bf16", "fp32"):
+            assert P.footprint(plan, prec) > out_bytes

@@ -1,0 +1,123 @@
+"""GPU tests of the request loop (blr_server_*): FIFO admission by free slot and HBM
+budget, jobs running concurrently on the slots' streams.
+
+* Every job's U, V, Atil, B in a concurrent mix equal its solo blr_tag_compress run bit
+  for bit (a job's arithmetic never depends on the other jobs).
+* With a budget that fits only one of two jobs, their device intervals never overlap.
+* A job larger than the whole budget is refused with BLR_ERR_BUSY.
+* Poisson arrivals (seeded) all complete; latency percentiles are reported.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    import torch
+    import paper_2501_05528_amd as P
+    out = []
+    precs = ["bf16", "fp64", "fp32"]
+    for q, wl in enumerate(W.uneven_batch_jobs(6, 20250105, n_lo=2048, n_hi=8192)):
+        g = wl.geometry()
+        near = O.near_lists(g.lattice)
+        T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, 3))
+        G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+        gu, gv = W.refinement_gammas(wl.seed, g.nboxes, wl.r, wl.r)
+        plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=3)
+        out.append(dict(plan=plan, op=P.Operator.kernel(wl.kind, g.pts), G=P.colmajor(G), H=P.colmajor(H),
+                        gamma_u=torch.as_tensor(gu, device="cuda"), gamma_v=torch.as_tensor(gv, device="cuda"),
+                        precision=precs[q % 3], n=g.n, kind=wl.kind, k=wl.k))
+        _announce(f"serve job {q}: N={g.n} k={wl.k} {wl.kind} {precs[q % 3]}")
+    return out
+
+
+def _kw(j):
+    return {} if j["precision"] == "fp64" else dict(precision=j["precision"], gamma_u=j["gamma_u"],
+                                                    gamma_v=j["gamma_v"])
+
+
+def _parts(h):
+    return {x: h.part(x) for x in ("U", "V", "Atil", "B")}
+
+
+def test_alone_equals_mix(jobs):
+    import torch
+    import paper_2501_05528_amd as P
+    solo = []
+    for j in jobs:
+        h, _ = P.compress(j["plan"], j["op"], j["G"], j["H"], **_kw(j))
+        solo.append(_parts(h))
+    torch.cuda.synchronize()
+    srv = P.Server(hbm_budget=64 << 30, slots=4)
+    tickets = [srv.submit(j["plan"], j["op"], j["G"], j["H"], **_kw(j)) for j in jobs]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    overlap = 0
+    for q, (h, st) in enumerate(results):
+        assert st["status"] == 0
+        got = _parts(h)
+        for x in ("U", "V", "Atil", "B"):
+            assert (got[x] == solo[q][x]).all().item(), (q, x)
+        for q2, (_, st2) in enumerate(results):
+            if q2 != q and st["t_start"] < st2["t_end"] and st2["t_start"] < st["t_end"]:
+                overlap += 1
+    _announce(f"mix of {len(jobs)} jobs on 4 slots: {overlap // 2} overlapping pairs")
+
+
+def test_budget_serialises(jobs):
+    import paper_2501_05528_amd as P
+    a, b = jobs[0], jobs[1]
+    fa = P.footprint(a["plan"], a["precision"], a["G"].shape[1] if a["precision"] != "fp64" else 0)
+    fb = P.footprint(b["plan"], b["precision"], b["G"].shape[1] if b["precision"] != "fp64" else 0)
+    srv = P.Server(hbm_budget=max(fa, fb) + min(fa, fb) // 2, slots=4)
+    ta = srv.submit(a["plan"], a["op"], a["G"], a["H"], **_kw(a))
+    tb = srv.submit(b["plan"], b["op"], b["G"], b["H"], **_kw(b))
+    (_, sa), (_, sb) = srv.wait(ta), srv.wait(tb)
+    srv.close()
+    assert sa["t_end"] <= sb["t_start"] or sb["t_end"] <= sa["t_start"]
+    assert sb["t_start"] >= sa["t_start"]            # FIFO
+
+
+def test_over_budget_refused(jobs):
+    import paper_2501_05528_amd as P
+    j = jobs[0]
+    srv = P.Server(hbm_budget=1 << 20, slots=2)
+    with pytest.raises(P.BlrError) as ei:
+        srv.submit(j["plan"], j["op"], j["G"], j["H"], **_kw(j))
+    assert ei.value.name == "BLR_ERR_BUSY"
+    srv.close()
+
+
+def test_poisson_arrivals(jobs):
+    import paper_2501_05528_amd as P
+    rng = W.rng(20250105, W.STREAM_ARRIVALS)
+    gaps = rng.exponential(1.0 / 200.0, size=24)
+    srv = P.Server(hbm_budget=64 << 30, slots=4)
+    tickets = []
+    t = time.monotonic()
+    for q, gap in enumerate(gaps):
+        t += gap
+        while time.monotonic() < t:
+            time.sleep(0.0005)
+        j = jobs[q % len(jobs)]
+        tickets.append(srv.submit(j["plan"], j["op"], j["G"], j["H"], **_kw(j)))
+    lat = []
+    for tk in tickets:
+        _, st = srv.wait(tk)
+        assert st["status"] == 0
+        lat.append(st["t_end"] - st["t_submit"])
+    srv.close()
+    p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+    _announce(f"24 Poisson arrivals at 200/s: p50 {1e3 * p50:.1f} ms, p99 {1e3 * p99:.1f} ms")
+    assert p50 > 0 and p99 >= p50
