@@ -1211,6 +1211,7 @@ blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t fl
                 j.SY = B->alloc<double>(P.n * P.r);
                 j.SZ = B->alloc<double>(P.n * P.r);
                 j.persistent = o.type == OpType::Kernel;
+                if (j.persistent && P.n >= (int64_t(1) << 31)) fail(BLR_ERR_UNSUPPORTED, "N >= 2^31 in a batch");
             } else {
                 j.Y = B->alloc<double>(P.n * LR);
                 j.Z = B->alloc<double>(P.n * LR);

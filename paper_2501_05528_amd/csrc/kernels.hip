@@ -825,7 +825,6 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     extern __shared__ double smem[];
     __shared__ double rdiag[128], vvs[128], norms[128];
     __shared__ int order[128];
-    __shared__ int changed;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int side = blockIdx.x >= nbox ? 1 : 0;
@@ -889,56 +888,59 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     }
     __syncthreads();
     // 2. one-sided Jacobi on the columns of Rt, rotations accumulated in J
-    // (skipped in QR-only mode: then U = the first k columns of Q)
+    // (skipped in QR-only mode: then U = the first k columns of Q).  One wave runs
+    // it: each round's nr/2 column pairs (round-robin order) are disjoint, so lane u
+    // rotates pair u on its own, with no cross-lane reduction.
     const double tol = sqrt(static_cast<double>(r)) * 2.220446049250313e-16;
     const int nr = r + (r & 1);
-    for (int sweep = 0; sweep < (qr_only ? 0 : max_sweeps); ++sweep) {
-        if (tid == 0) changed = 0;
-        __syncthreads();
-        for (int round = 0; round < nr - 1; ++round) {
-            for (int u = wave; u < nr / 2; u += 4) {
-                int p = rr_player(u, round, nr), q = rr_player(nr - 1 - u, round, nr);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                if (q >= r) continue;
-                double* xp = Rt + p * r;
-                double* xq = Rt + q * r;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int a = lane; a < r; a += 64) {
-                    const double x = xp[a], y = xq[a];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
-                }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                    double* jp = J + p * r;
-                    double* jq = J + q * r;
-                    for (int a = lane; a < r; a += 64) {
-                        const double x = xp[a], y = xq[a];
-                        xp[a] = c * x - sn * y;
-                        xq[a] = sn * x + c * y;
-                        const double u1 = jp[a], u2 = jq[a];
-                        jp[a] = c * u1 - sn * u2;
-                        jq[a] = sn * u1 + c * u2;
+    if (!qr_only && wave == 0) {
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+            int rotated = 0;
+            for (int round = 0; round < nr - 1; ++round) {
+                if (lane < nr / 2) {
+                    int p = rr_player(lane, round, nr), q = rr_player(nr - 1 - lane, round, nr);
+                    if (p > q) {
+                        const int t = p;
+                        p = q;
+                        q = t;
                     }
-                    if (lane == 0) changed = 1;
+                    if (q < r) {
+                        double* xp = Rt + p * r;
+                        double* xq = Rt + q * r;
+                        double al = 0.0, be = 0.0, ga = 0.0;
+                        for (int a = 0; a < r; ++a) {
+                            const double x = xp[a], y = xq[a];
+                            al = fma(x, x, al);
+                            be = fma(y, y, be);
+                            ga = fma(x, y, ga);
+                        }
+                        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                            const double zeta = (be - al) / (2.0 * ga);
+                            const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+                            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                            double* jp = J + p * r;
+                            double* jq = J + q * r;
+                            for (int a = 0; a < r; ++a) {
+                                const double x = xp[a], y = xq[a];
+                                xp[a] = c * x - sn * y;
+                                xq[a] = sn * x + c * y;
+                                const double u1 = jp[a], u2 = jq[a];
+                                jp[a] = c * u1 - sn * u2;
+                                jq[a] = sn * u1 + c * u2;
+                            }
+                            rotated = 1;
+                        }
+                    }
                 }
+                // this round's LDS writes precede the next round's reads by other lanes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __syncthreads();
+            if (!__any(rotated)) break;
         }
-        const int ch = changed;
-        __syncthreads();
-        if (!ch) break;
     }
+    __syncthreads();
     // 3. singular values and their order
     for (int c = wave; c < r; c += 4) {
         double s2 = 0.0;

@@ -16,12 +16,26 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uv4 __attribute__((ext_vector_type(4)));
 
 constexpr int LP_KT = 32;  // sources per K step: one 16x16x32 BF16 MFMA deep
+
 
 void check_launch_lp(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) fail(BLR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Address-space qualifiers: the tile body takes LDS tiles as LDS pointers and
+// every array in device memory as a global pointer, so the compiler emits ds_*
+// and global_* instructions (not flat ones) also when the pointers come from a
+// job descriptor in memory.
+#define BLR_LDS __attribute__((address_space(3)))
+#define BLR_GLB __attribute__((address_space(1)))
+template <class T>
+__host__ __device__ inline BLR_GLB T* gptr(T* p) {
+    return (BLR_GLB T*)p;
 }
 
 // ------------------------------------------------------------ FP32 entries
@@ -44,16 +58,16 @@ __device__ inline float kval32(float r2) {
 
 template <int KIND>
 struct KernelSrc32 {
-    const float* px;
-    const float* py;
-    const float* pz;
+    const BLR_GLB float* px;
+    const BLR_GLB float* py;
+    const BLR_GLB float* pz;
     float diag;
     struct P {
         float x, y, z;
-        int64_t i;
+        int32_t i;  // row index (N < 2^31 is checked at launch)
     };
-    __device__ P row(int64_t i) const { return P{px[i], py[i], pz[i], i}; }
-    __device__ P col(int64_t j) const { return P{px[j], py[j], pz[j], j}; }
+    __device__ P row(int64_t i) const { return P{px[i], py[i], pz[i], static_cast<int32_t>(i)}; }
+    __device__ P col(int64_t j) const { return P{px[j], py[j], pz[j], static_cast<int32_t>(j)}; }
     __device__ float val(const P& a, const P& b) const {
         const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
         const float v = kval32<KIND>(dx * dx + dy * dy + dz * dz);
@@ -166,21 +180,21 @@ struct LpTile {
 // column group grp.  sAp / sBp: double-buffered LDS tiles (2 x BM*AST floats, 2 x BEL
 // elements), 16-byte aligned.
 template <class AS, int PREC, int NTR, int NSIDE, int SPW>
-__device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
-                                      const int64_t* __restrict__ box_ptr, int nbox,
-                                      const typename LpElem<PREC>::T* __restrict__ B0,
-                                      const typename LpElem<PREC>::T* __restrict__ B1, int64_t n,
-                                      int r, int ell, float* __restrict__ Y0, float* __restrict__ Y1,
-                                      int64_t rt_blk, int grp, float* sAp,
-                                      typename LpElem<PREC>::T* sBp) {
+__device__ __attribute__((always_inline)) inline void sketch_lp_tile(AS A, const BLR_GLB float* __restrict__ Tf,
+                                      const BLR_GLB int64_t* __restrict__ box_ptr, int nbox,
+                                      const BLR_GLB typename LpElem<PREC>::T* __restrict__ B0,
+                                      const BLR_GLB typename LpElem<PREC>::T* __restrict__ B1, int64_t n,
+                                      int r, int ell, BLR_GLB float* __restrict__ Y0, BLR_GLB float* __restrict__ Y1,
+                                      int64_t rt_blk, int grp, BLR_LDS float* sAp,
+                                      BLR_LDS typename LpElem<PREC>::T* sBp) {
     using E = typename LpElem<PREC>::T;
     using TL = LpTile<PREC, NTR, NSIDE>;
     constexpr int BM = TL::BM, KT = TL::KT, AST = TL::AST, FRAG = TL::FRAG, BEL = TL::BEL;
     constexpr int CH_EL = 16 / sizeof(E);                      // elements per 16-byte chunk
     constexpr int NCH = BEL / CH_EL;                           // 16-byte chunks per step
     constexpr int CPT = (NCH + 255) / 256;                     // chunks per thread
-    float (*sA)[BM * AST] = reinterpret_cast<float (*)[BM * AST]>(sAp);
-    E (*sB)[BEL] = reinterpret_cast<E (*)[BEL]>(sBp);
+    BLR_LDS float (*sA)[BM * AST] = reinterpret_cast<BLR_LDS float (*)[BM * AST]>(sAp);
+    BLR_LDS E (*sB)[BEL] = reinterpret_cast<BLR_LDS E (*)[BEL]>(sBp);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rt = wave & 1, half = wave >> 1;
@@ -194,7 +208,7 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
     const int64_t gi = row0 + arow;
     const auto rp = A.row(gi < n ? gi : n - 1);
 
-    uint4 bv[CPT];
+    uint64_t bv[CPT][2];
     auto fetch_b = [&](int64_t t) {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
@@ -202,8 +216,10 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
             if (ch < NCH) {
                 const int el = ch * CH_EL;                 // element within the step block
                 const int sd = el / (NTR * FRAG);
-                const E* src = (sd ? B1 : B0) + t * (NTR * FRAG) + (el - sd * NTR * FRAG);
-                bv[u] = *reinterpret_cast<const uint4*>(src);
+                const BLR_GLB E* src = (sd ? B1 : B0) + t * (NTR * FRAG) + (el - sd * NTR * FRAG);
+                const BLR_GLB uint64_t* q = reinterpret_cast<const BLR_GLB uint64_t*>(src);
+                bv[u][0] = q[0];
+                bv[u][1] = q[1];
             }
         }
     };
@@ -211,7 +227,11 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int ch = tid + 256 * u;
-            if (ch < NCH) *reinterpret_cast<uint4*>(&sB[buf][ch * CH_EL]) = bv[u];
+            if (ch < NCH) {
+                BLR_LDS uint64_t* q = reinterpret_cast<BLR_LDS uint64_t*>(&sB[buf][ch * CH_EL]);
+                q[0] = bv[u][0];
+                q[1] = bv[u][1];
+            }
         }
     };
     // the next step's kernel columns are loaded before the current step's MFMAs
@@ -275,9 +295,9 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
         // this wave's A fragment: row rt*16 + lane % 16, sources 8 (lane / 16) + e
         float af[8];
         {
-            const float* ap = &sA[buf][(rt * 16 + (lane & 15)) * AST + 8 * (lane >> 4)];
-            const float4 lo = *reinterpret_cast<const float4*>(ap);
-            const float4 hi = *reinterpret_cast<const float4*>(ap + 4);
+            const BLR_LDS float* ap = &sA[buf][(rt * 16 + (lane & 15)) * AST + 8 * (lane >> 4)];
+            const fv4 lo = *reinterpret_cast<const BLR_LDS fv4*>(ap);
+            const fv4 hi = *reinterpret_cast<const BLR_LDS fv4*>(ap + 4);
             af[0] = lo.x; af[1] = lo.y; af[2] = lo.z; af[3] = lo.w;
             af[4] = hi.x; af[5] = hi.y; af[6] = hi.z; af[7] = hi.w;
         }
@@ -287,7 +307,7 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
             for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
                 for (int nt = 0; nt < NTR; ++nt)
-                    bq[sd][nt] = *reinterpret_cast<const bf16x8*>(&sB[buf][((sd * NTR + nt) * 64 + lane) * 8]);
+                    bq[sd][nt] = *reinterpret_cast<const BLR_LDS bf16x8*>(&sB[buf][((sd * NTR + nt) * 64 + lane) * 8]);
 #pragma unroll
             for (int v = 0; v < SPW; ++v) {
                 if (v < nsv) {
@@ -307,9 +327,9 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
             for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
                 for (int nt = 0; nt < NTR; ++nt) {
-                    const float* bp = &sB[buf][((sd * NTR + nt) * 64 + lane) * 8];
-                    const float4 lo = *reinterpret_cast<const float4*>(bp);
-                    const float4 hi = *reinterpret_cast<const float4*>(bp + 4);
+                    const BLR_LDS float* bp = &sB[buf][((sd * NTR + nt) * 64 + lane) * 8];
+                    const fv4 lo = *reinterpret_cast<const BLR_LDS fv4*>(bp);
+                    const fv4 hi = *reinterpret_cast<const BLR_LDS fv4*>(bp + 4);
                     bq[sd][nt][0] = lo.x; bq[sd][nt][1] = lo.y; bq[sd][nt][2] = lo.z; bq[sd][nt][3] = lo.w;
                     bq[sd][nt][4] = hi.x; bq[sd][nt][5] = hi.y; bq[sd][nt][6] = hi.z; bq[sd][nt][7] = hi.w;
                 }
@@ -348,7 +368,7 @@ __device__ inline void sketch_lp_tile(AS A, const float* __restrict__ Tf,
         const int sv = s_lo + v;
 #pragma unroll
         for (int sd = 0; sd < NSIDE; ++sd) {
-            float* Yo = sd ? Y1 : Y0;
+            BLR_GLB float* Yo = sd ? Y1 : Y0;
 #pragma unroll
             for (int nt = 0; nt < NTR; ++nt) {
                 const int c = nt * 16 + (lane & 15);
@@ -372,8 +392,9 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp(AS A, const float* __restr
     using TL = LpTile<PREC, NTR, NSIDE>;
     __shared__ __attribute__((aligned(16))) float sA[2 * TL::BM * TL::AST];
     __shared__ __attribute__((aligned(16))) typename TL::E sB[2 * TL::BEL];
-    sketch_lp_tile<AS, PREC, NTR, NSIDE, SPW>(A, Tf, box_ptr, nbox, B0, B1, n, r, ell, Y0, Y1,
-                                              blockIdx.x, blockIdx.y, sA, sB);
+    sketch_lp_tile<AS, PREC, NTR, NSIDE, SPW>(A, gptr(Tf), gptr(box_ptr), nbox, gptr(B0), gptr(B1), n, r,
+                                              ell, gptr(Y0), gptr(Y1), blockIdx.x, blockIdx.y,
+                                              (BLR_LDS float*)sA, (BLR_LDS typename TL::E*)sB);
 }
 
 // Persistent form over a batch of kernel-matrix jobs: workgroups stride over a
@@ -387,33 +408,42 @@ __global__ __launch_bounds__(256, 2) void k_sketch_lp_multi(const LpJob* __restr
     using E = typename TL::E;
     __shared__ __attribute__((aligned(16))) float sA[2 * TL::BM * TL::AST];
     __shared__ __attribute__((aligned(16))) E sB[2 * TL::BEL];
+    BLR_LDS float* lA = (BLR_LDS float*)sA;
+    BLR_LDS E* lB = (BLR_LDS E*)sB;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
         const LpJob& J = jobs[w.x];
         const int64_t rt_blk = static_cast<int64_t>(w.y);
-        const E* b0 = static_cast<const E*>(J.B0);
-        const E* b1 = static_cast<const E*>(J.B1);
+        const BLR_GLB E* b0 = gptr(static_cast<const E*>(J.B0));
+        const BLR_GLB E* b1 = gptr(static_cast<const E*>(J.B1));
+        const BLR_GLB float* px = gptr(J.px);
+        const BLR_GLB float* py = gptr(J.py);
+        const BLR_GLB float* pz = gptr(J.pz);
+        const BLR_GLB float* Tf = gptr(J.Tf);
+        const BLR_GLB int64_t* bptr = gptr(J.box_ptr);
+        BLR_GLB float* Y0 = gptr(J.Y0);
+        BLR_GLB float* Y1 = gptr(J.Y1);
         __syncthreads();  // the previous item's last reads of LDS are done
         switch (J.kind) {
             case BLR_KERNEL_LOG:
                 sketch_lp_tile<KernelSrc32<BLR_KERNEL_LOG>, PREC, NTR, 2, SPW>(
-                    KernelSrc32<BLR_KERNEL_LOG>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
-                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                    KernelSrc32<BLR_KERNEL_LOG>{px, py, pz, J.diag}, Tf, bptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, Y0, Y1, rt_blk, w.z, lA, lB);
                 break;
             case BLR_KERNEL_INV_R:
                 sketch_lp_tile<KernelSrc32<BLR_KERNEL_INV_R>, PREC, NTR, 2, SPW>(
-                    KernelSrc32<BLR_KERNEL_INV_R>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
-                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                    KernelSrc32<BLR_KERNEL_INV_R>{px, py, pz, J.diag}, Tf, bptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, Y0, Y1, rt_blk, w.z, lA, lB);
                 break;
             case BLR_KERNEL_EXP:
                 sketch_lp_tile<KernelSrc32<BLR_KERNEL_EXP>, PREC, NTR, 2, SPW>(
-                    KernelSrc32<BLR_KERNEL_EXP>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
-                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                    KernelSrc32<BLR_KERNEL_EXP>{px, py, pz, J.diag}, Tf, bptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, Y0, Y1, rt_blk, w.z, lA, lB);
                 break;
             default:
                 sketch_lp_tile<KernelSrc32<BLR_KERNEL_COS>, PREC, NTR, 2, SPW>(
-                    KernelSrc32<BLR_KERNEL_COS>{J.px, J.py, J.pz, J.diag}, J.Tf, J.box_ptr, J.nbox, b0, b1,
-                    J.n, J.r, J.ell, J.Y0, J.Y1, rt_blk, w.z, sA, sB);
+                    KernelSrc32<BLR_KERNEL_COS>{px, py, pz, J.diag}, Tf, bptr, J.nbox, b0, b1,
+                    J.n, J.r, J.ell, Y0, Y1, rt_blk, w.z, lA, lB);
                 break;
         }
     }
@@ -520,9 +550,10 @@ void launch_sketch_lp(const OpData& op, const PlanData& P, const DeviceTables& t
     auto run = [&](auto prec_tag) {
         constexpr int PREC = decltype(prec_tag)::value;
         if (op.type == OpType::Kernel) {
-            const float* px = op.pts32;
-            const float* py = op.pts32 + op.n;
-            const float* pz = op.pts32 + 2 * op.n;
+            if (op.n >= (int64_t(1) << 31)) fail(BLR_ERR_UNSUPPORTED, "N >= 2^31 in the low-precision sketch");
+            const BLR_GLB float* px = gptr(op.pts32);
+            const BLR_GLB float* py = gptr(op.pts32 + op.n);
+            const BLR_GLB float* pz = gptr(op.pts32 + 2 * op.n);
             auto go = [&](auto A) { sketch_lp_launch<PREC>(A, P, t, r_lo, PG, PH, 2, Y, Z, s); };
             switch (op.kind) {
                 case BLR_KERNEL_LOG: go(KernelSrc32<BLR_KERNEL_LOG>{px, py, pz, 0.0f}); break;
@@ -545,8 +576,9 @@ void launch_sketch_lp(const OpData& op, const PlanData& P, const DeviceTables& t
 }
 
 int lp_multi_spw_candidates(int precision, int ntr, int* spw) {
-    static const int bf16[6][2] = {{0, 0}, {8, 4}, {8, 4}, {7, 4}, {5, 3}, {4, 2}};
-    static const int fp32[6][2] = {{0, 0}, {8, 4}, {7, 4}, {5, 3}, {3, 2}, {3, 2}};
+    // (candidates keep the persistent kernel free of register spills)
+    static const int bf16[6][2] = {{0, 0}, {8, 4}, {8, 4}, {6, 4}, {4, 3}, {3, 2}};
+    static const int fp32[6][2] = {{0, 0}, {8, 4}, {7, 4}, {4, 3}, {3, 2}, {2, 1}};
     if (ntr < 1 || ntr > 5) fail(BLR_ERR_UNSUPPORTED, "r_lo > 80 is not supported by the low-precision sketch");
     const int(*tab)[2] = precision == BLR_PREC_BF16_REFINE ? bf16 : fp32;
     spw[0] = tab[ntr][0];
@@ -566,14 +598,14 @@ void launch_sketch_lp_multi(int precision, int ntr, int spw, const LpJob* jobs, 
     }
     BLR_LPM(BLR_PREC_BF16_REFINE, 1, 8) BLR_LPM(BLR_PREC_BF16_REFINE, 1, 4)
     BLR_LPM(BLR_PREC_BF16_REFINE, 2, 8) BLR_LPM(BLR_PREC_BF16_REFINE, 2, 4)
-    BLR_LPM(BLR_PREC_BF16_REFINE, 3, 7) BLR_LPM(BLR_PREC_BF16_REFINE, 3, 4)
-    BLR_LPM(BLR_PREC_BF16_REFINE, 4, 5) BLR_LPM(BLR_PREC_BF16_REFINE, 4, 3)
-    BLR_LPM(BLR_PREC_BF16_REFINE, 5, 4) BLR_LPM(BLR_PREC_BF16_REFINE, 5, 2)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 3, 6) BLR_LPM(BLR_PREC_BF16_REFINE, 3, 4)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 4, 4) BLR_LPM(BLR_PREC_BF16_REFINE, 4, 3)
+    BLR_LPM(BLR_PREC_BF16_REFINE, 5, 3) BLR_LPM(BLR_PREC_BF16_REFINE, 5, 2)
     BLR_LPM(BLR_PREC_FP32_REFINE, 1, 8) BLR_LPM(BLR_PREC_FP32_REFINE, 1, 4)
     BLR_LPM(BLR_PREC_FP32_REFINE, 2, 7) BLR_LPM(BLR_PREC_FP32_REFINE, 2, 4)
-    BLR_LPM(BLR_PREC_FP32_REFINE, 3, 5) BLR_LPM(BLR_PREC_FP32_REFINE, 3, 3)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 3, 4) BLR_LPM(BLR_PREC_FP32_REFINE, 3, 3)
     BLR_LPM(BLR_PREC_FP32_REFINE, 4, 3) BLR_LPM(BLR_PREC_FP32_REFINE, 4, 2)
-    BLR_LPM(BLR_PREC_FP32_REFINE, 5, 3) BLR_LPM(BLR_PREC_FP32_REFINE, 5, 2)
+    BLR_LPM(BLR_PREC_FP32_REFINE, 5, 2) BLR_LPM(BLR_PREC_FP32_REFINE, 5, 1)
 #undef BLR_LPM
     fail(BLR_ERR_INVALID_ARG, "no persistent sketch for this precision, column tiles and SPW");
 }

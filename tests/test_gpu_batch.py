@@ -16,8 +16,8 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-SPW_CANDIDATES = {2: {1: (8, 4), 2: (8, 4), 3: (7, 4), 4: (5, 3), 5: (4, 2)},
-                  1: {1: (8, 4), 2: (7, 4), 3: (5, 3), 4: (3, 2), 5: (3, 2)}}
+SPW_CANDIDATES = {2: {1: (8, 4), 2: (8, 4), 3: (6, 4), 4: (4, 3), 5: (3, 2)},
+                  1: {1: (8, 4), 2: (7, 4), 3: (4, 3), 4: (3, 2), 5: (2, 1)}}
 
 
 def _announce(msg):
