@@ -86,6 +86,46 @@ __device__ inline double log_pos(double x) {
     return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, lm));
 }
 
+#define BLR_LDS __attribute__((address_space(3)))
+
+// Table-driven natural logarithm for the kernel-matrix entries.  x = m 2^e with
+// m in [1/sqrt2, sqrt2); the top six mantissa bits of m (and its binade) pick one
+// of 128 centres c with r = 1/c stored beside L = -ln r, so that
+//   ln x = e ln2 + L + ln(1 + f),   f = m r - 1 (one fused multiply-add, |f| <= 2^-7),
+// with ln(1 + f) from its Taylor series to f^8 (truncation below 1e-20).  The table
+// is built per workgroup from log_pos.  Absolute error about 2e-16 for |ln x| < 1.
+__device__ inline void build_log_table(BLR_LDS double* tab) {
+    const int t = threadIdx.x;
+    if (t < 128) {
+        const double base = t < 64 ? 0.5 : 1.0;
+        const double c = base * (1.0 + ((t & 63) + 0.5) / 64.0);
+        const double r = 1.0 / c;
+        tab[2 * t] = r;
+        tab[2 * t + 1] = -log_pos(r);
+    }
+}
+
+__device__ inline double log_tab(double x, const BLR_LDS double* tab) {
+    const int e0 = __builtin_amdgcn_frexp_exp(x);
+    double m = __builtin_amdgcn_frexp_mant(x);
+    const bool lo = m < 0.7071067811865476;
+    m = lo ? 2.0 * m : m;
+    const int e = lo ? e0 - 1 : e0;
+    const int idx = ((__double2hiint(m) >> 14) & 63) + (m >= 1.0 ? 64 : 0);
+    const double r = tab[2 * idx], L = tab[2 * idx + 1];
+    const double f = fma(m, r, -1.0);
+    double q = -1.0 / 8.0;
+    q = fma(q, f, 1.0 / 7.0);
+    q = fma(q, f, -1.0 / 6.0);
+    q = fma(q, f, 1.0 / 5.0);
+    q = fma(q, f, -1.0 / 4.0);
+    q = fma(q, f, 1.0 / 3.0);
+    q = fma(q, f, -0.5);
+    const double l1 = fma(f * f, q, f);
+    const double de = static_cast<double>(e);
+    return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, L + l1));
+}
+
 template <int KIND>
 __device__ inline double kval(double r2) {
     if constexpr (KIND == BLR_KERNEL_LOG) {
@@ -106,6 +146,14 @@ struct KernelSrc {
     const double* py;
     const double* pz;
     double diag;
+    const BLR_LDS double* ltab = nullptr;  // log table in LDS (log kernel), set by prepare()
+    // once per workgroup, before any entry (a __syncthreads() must follow)
+    __device__ void prepare(BLR_LDS double* tab) {
+        if constexpr (KIND == BLR_KERNEL_LOG) {
+            build_log_table(tab);
+            ltab = tab;
+        }
+    }
     struct P {
         double x, y, z;
         int64_t i;
@@ -114,7 +162,12 @@ struct KernelSrc {
     __device__ P col(int64_t j) const { return P{px[j], py[j], pz[j], j}; }
     __device__ double val(const P& a, const P& b) const {
         double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-        double v = kval<KIND>(dx * dx + dy * dy + dz * dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double v;
+        if constexpr (KIND == BLR_KERNEL_LOG)
+            v = 0.5 * log_tab(r2, ltab);
+        else
+            v = kval<KIND>(r2);
         return a.i == b.i ? diag : v;
     }
     // column contexts staged through LDS: 3 doubles per column
@@ -135,6 +188,7 @@ struct KernelSrc {
 struct DenseSrc {  // A(i, j) = A[i + j*lda]
     const double* A;
     int64_t lda;
+    __device__ void prepare(BLR_LDS double*) {}
     struct P {
         int64_t i;
     };
@@ -152,6 +206,7 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
 struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
     const double* A;
     int64_t lda;
+    __device__ void prepare(BLR_LDS double*) {}
     struct P {
         int64_t i;
     };
@@ -228,6 +283,9 @@ struct SplitOut {  // column q < LR -> C0(:, q), else C1(:, q - LR)
 template <class AS, class BS, class OUT, int WN>
 __global__ __launch_bounds__(256, 2) void k_opgemm(AS A, BS B, OUT O, int64_t M, int64_t K,
                                                     int ncols) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int BM = 64, KT = 8, BN = 4 * WN, NT = WN / 16;
     constexpr int BPT = KT * BN / 256;  // B tile entries per thread
     static_assert((KT * BN) % 256 == 0, "B tile must split evenly over 256 threads");
@@ -373,6 +431,9 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
                                                     const double* __restrict__ G1, int64_t n,
                                                     int r, int ell, double* __restrict__ Y0,
                                                     double* __restrict__ Y1) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int MA = 2, BM = 4 * MA, KT = 16, CW = NTR * 16;  // rows, sources/step, cols/side
     constexpr int BW = NSIDE * CW;                               // B tile width
     constexpr int BPT = (KT * BW + 255) / 256;
@@ -606,6 +667,9 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
                                                    const double* __restrict__ X0,
                                                    const double* __restrict__ X1, int64_t n, int r,
                                                    double* __restrict__ S0, double* __restrict__ S1) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int BM = 64, MA = 4, KT = 16, CW = NTR * 16, BW = NSIDE * CW;
     constexpr int BPT = (KT * BW + 255) / 256;
     __shared__ double sA[2][KT * BM];
@@ -888,59 +952,60 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     }
     __syncthreads();
     // 2. one-sided Jacobi on the columns of Rt, rotations accumulated in J
-    // (skipped in QR-only mode: then U = the first k columns of Q).  One wave runs
-    // it: each round's nr/2 column pairs (round-robin order) are disjoint, so lane u
-    // rotates pair u on its own, with no cross-lane reduction.
+    // (skipped in QR-only mode: then U = the first k columns of Q).  Each round's
+    // nr/2 column pairs (round-robin order) are disjoint; a group of 16 lanes
+    // rotates one pair, its lanes striding over the r entries and reducing the
+    // three inner products with in-group shuffles; 16 groups share a round.
     const double tol = sqrt(static_cast<double>(r)) * 2.220446049250313e-16;
     const int nr = r + (r & 1);
-    if (!qr_only && wave == 0) {
-        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-            int rotated = 0;
-            for (int round = 0; round < nr - 1; ++round) {
-                if (lane < nr / 2) {
-                    int p = rr_player(lane, round, nr), q = rr_player(nr - 1 - lane, round, nr);
-                    if (p > q) {
-                        const int t = p;
-                        p = q;
-                        q = t;
-                    }
-                    if (q < r) {
-                        double* xp = Rt + p * r;
-                        double* xq = Rt + q * r;
-                        double al = 0.0, be = 0.0, ga = 0.0;
-                        for (int a = 0; a < r; ++a) {
-                            const double x = xp[a], y = xq[a];
-                            al = fma(x, x, al);
-                            be = fma(y, y, be);
-                            ga = fma(x, y, ga);
-                        }
-                        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                            const double zeta = (be - al) / (2.0 * ga);
-                            const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
-                            const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                            double* jp = J + p * r;
-                            double* jq = J + q * r;
-                            for (int a = 0; a < r; ++a) {
-                                const double x = xp[a], y = xq[a];
-                                xp[a] = c * x - sn * y;
-                                xq[a] = sn * x + c * y;
-                                const double u1 = jp[a], u2 = jq[a];
-                                jp[a] = c * u1 - sn * u2;
-                                jq[a] = sn * u1 + c * u2;
-                            }
-                            rotated = 1;
-                        }
-                    }
+    const int grp = tid >> 4, gl = tid & 15;
+    for (int sweep = 0; sweep < (qr_only ? 0 : max_sweeps); ++sweep) {
+        int rotated = 0;
+        for (int round = 0; round < nr - 1; ++round) {
+            for (int u = grp; u < nr / 2; u += 16) {
+                int p = rr_player(u, round, nr), q = rr_player(nr - 1 - u, round, nr);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
                 }
-                // this round's LDS writes precede the next round's reads by other lanes
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (q >= r) continue;
+                double* xp = Rt + p * r;
+                double* xq = Rt + q * r;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int a = gl; a < r; a += 16) {
+                    const double x = xp[a], y = xq[a];
+                    al = fma(x, x, al);
+                    be = fma(y, y, be);
+                    ga = fma(x, y, ga);
+                }
+#pragma unroll
+                for (int o = 8; o >= 1; o >>= 1) {
+                    al += __shfl_xor(al, o, 16);
+                    be += __shfl_xor(be, o, 16);
+                    ga += __shfl_xor(ga, o, 16);
+                }
+                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    double* jp = J + p * r;
+                    double* jq = J + q * r;
+                    for (int a = gl; a < r; a += 16) {
+                        const double x = xp[a], y = xq[a];
+                        xp[a] = c * x - sn * y;
+                        xq[a] = sn * x + c * y;
+                        const double u1 = jp[a], u2 = jq[a];
+                        jp[a] = c * u1 - sn * u2;
+                        jq[a] = sn * u1 + c * u2;
+                    }
+                    rotated = 1;
+                }
             }
-            if (!__any(rotated)) break;
+            __syncthreads();
         }
+        if (!__syncthreads_or(rotated)) break;
     }
-    __syncthreads();
     // 3. singular values and their order
     for (int c = wave; c < r; c += 4) {
         double s2 = 0.0;
@@ -1005,6 +1070,9 @@ __global__ __launch_bounds__(256, (NT >= 4 ? 1 : 2)) void k_cores(AS A, const in
                                                   const double* __restrict__ U,
                                                   const double* __restrict__ V, int64_t ldUV,
                                                   int k, double* __restrict__ Atil, int64_t ldAt) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int KT = 16, RC = 256, KP = NT * 16;
     __shared__ double sA[KT * RC];
     __shared__ double sV[KT * KP];
@@ -1102,6 +1170,9 @@ template <class AS, int NT>
 __global__ __launch_bounds__(256, 2) void k_cores_sym(
     AS A, const int64_t* __restrict__ box_ptr, const double* __restrict__ U,
     const double* __restrict__ V, int64_t ldUV, int k, double* __restrict__ Atil, int64_t ldAt) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int KT = 16, RC = 256, KP = NT * 16, NT2 = 2 * NT;
     __shared__ double sA[KT * RC];
     __shared__ double sV[KT * 2 * KP];
@@ -1269,6 +1340,9 @@ __global__ __launch_bounds__(256) void k_nf_b(
     const int32_t* __restrict__ colour_boxes, const int32_t* __restrict__ nf_pair, int ncol,
     const double* __restrict__ U, int64_t ldUV, int k, int m_max, const double* __restrict__ Qg,
     double* __restrict__ Bv) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int CW = 16, NB = 32;
     __shared__ double scol[NB * CW * AS::STAGE];
     __shared__ int64_t sidx[NB * CW];
@@ -1446,6 +1520,9 @@ __global__ __launch_bounds__(256) void k_err_fro(AS A, const int64_t* __restrict
                                                  const double* __restrict__ Atil, int64_t ldAt,
                                                  int k, const double* __restrict__ Bv,
                                                  double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
     constexpr int CH = 64;
     __shared__ double sV[CH * 64];
     __shared__ double red[2][4];
