@@ -657,10 +657,10 @@ void with_source(const OpData& op, int trans, F&& f) {
 //   S0(I_i, :) = sum_{l in F_i} A(I_i, I_l) X0(I_l, :)   and S1 from X1,
 // with the same kernel tile for both sides when the matrix is symmetric.  Near
 // blocks are masked to zero as the tile is generated; a source box that is
-// near to every row of the workgroup is skipped.  Workgroup: 64 target rows;
-// wave w owns rows 16w..16w+15 (four 4-row tiles of v_mfma_f64_4x4x4f64, the
-// layout of k_sketch) and every column tile of both sides.
-template <class AS, int NTR, int NSIDE>
+// near to every row of the workgroup is skipped.  Workgroup: 16 MA target rows;
+// wave w owns rows 4 MA w .. 4 MA (w + 1) - 1 (MA 4-row tiles of
+// v_mfma_f64_4x4x4f64, the layout of k_sketch) and every column tile of both sides.
+template <class AS, int NTR, int NSIDE, int MA>
 __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restrict__ box_ptr,
                                                    const int32_t* __restrict__ row_box,
                                                    const uint8_t* __restrict__ nearm, int nbox,
@@ -670,7 +670,8 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     __shared__ __attribute__((aligned(16))) double s_ltab[256];
     A.prepare((BLR_LDS double*)s_ltab);
     __syncthreads();
-    constexpr int BM = 64, MA = 4, KT = 16, CW = NTR * 16, BW = NSIDE * CW;
+    constexpr int BM = 16 * MA, KT = 16, CW = NTR * 16, BW = NSIDE * CW;
+    constexpr int KSTEP = 256 / BM;              // source stride of one thread's entries
     constexpr int BPT = (KT * BW + 255) / 256;
     __shared__ double sA[2][KT * BM];
     constexpr int KTP = KT + 1;                  // padded column stride of the B tile
@@ -681,8 +682,8 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     const int64_t rlast = min(row0 + BM, n) - 1;
     const int box_first = row_box[row0], box_last = row_box[rlast];
     const bool single = box_first == box_last;
-    // generation: thread owns row tid % 64 and sources tid / 64 + 4u, u < 4
-    const int arow = tid & 63, akk = tid >> 6;
+    // generation: thread owns row tid % BM and sources tid / BM + KSTEP u, u < MA
+    const int arow = tid % BM, akk = tid / BM;
     const int64_t gi = min(row0 + arow, n - 1);
     const auto rp = A.row(gi);
     const int64_t mybox_row = static_cast<int64_t>(row_box[gi]) * nbox;
@@ -717,20 +718,20 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     };
     // the next step's kernel columns and far mask are loaded before the current
     // step's MFMAs (pre_a) and turned into entries after them (gen_a)
-    typename AS::Pre apre[KT / 4];
+    typename AS::Pre apre[MA];
     bool far_pre = true;
     auto pre_a = [&](int l, int64_t jb, int64_t jend) {
         far_pre = nearm[mybox_row + l] == 0;
 #pragma unroll
-        for (int u = 0; u < KT / 4; ++u) {
-            const int64_t j = jb + akk + 4 * u;
+        for (int u = 0; u < MA; ++u) {
+            const int64_t j = jb + akk + KSTEP * u;
             apre[u] = A.pre(rp, j < jend ? j : jend - 1);
         }
     };
     auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
 #pragma unroll
-        for (int u = 0; u < KT / 4; ++u) {
-            const int kk = akk + 4 * u;
+        for (int u = 0; u < MA; ++u) {
+            const int kk = akk + KSTEP * u;
             const double v = A.fin(rp, apre[u]);
             sA[buf][kk * BM + arow] = (far_pre && jb + kk < jend) ? v : 0.0;
         }
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
                 const int kr = ks * 4 + (lane >> 4);
                 double a[MA];
 #pragma unroll
-                for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + wave * 16 + ma * 4 + (lane & 3)];
+                for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + wave * 4 * MA + ma * 4 + (lane & 3)];
                 double bb[NSIDE][NTR];
 #pragma unroll
                 for (int sd = 0; sd < NSIDE; ++sd)
@@ -806,7 +807,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
         double* So = sd ? S1 : S0;
 #pragma unroll
         for (int ma = 0; ma < MA; ++ma) {
-            const int64_t row = row0 + wave * 16 + ma * 4 + (lane >> 4);
+            const int64_t row = row0 + wave * 4 * MA + ma * 4 + (lane >> 4);
 #pragma unroll
             for (int nt = 0; nt < NTR; ++nt) {
                 const int c = nt * 16 + (lane & 15);
@@ -820,9 +821,10 @@ template <class AS>
 void refine_launch(AS A, const PlanData& P, const DeviceTables& t, const double* X0,
                    const double* X1, int nside, double* S0, double* S1, hipStream_t s) {
     const int ntr = (P.r + 15) / 16;
-    const dim3 grid(static_cast<unsigned>((P.n + 63) / 64));
-#define BLR_REFINE_CASE(NTRV, NSV)                                                                \
-    hipLaunchKernelGGL((k_refine<AS, NTRV, NSV>), grid, dim3(256), 0, s, A, t.box_ptr, t.row_box, \
+    constexpr int MAV = 4;  // 64 target rows per workgroup (32 measured slower)
+    const dim3 grid(static_cast<unsigned>((P.n + 16 * MAV - 1) / (16 * MAV)));
+#define BLR_REFINE_CASE(NTRV, NSV)                                                                      \
+    hipLaunchKernelGGL((k_refine<AS, NTRV, NSV, MAV>), grid, dim3(256), 0, s, A, t.box_ptr, t.row_box, \
                        t.nearm, P.b, X0, X1, P.n, P.r, S0, S1)
     if (nside == 2) {
         switch (ntr) {
