@@ -106,10 +106,44 @@ def run_mode(S, precision, steps, warmup, with_error):
     if with_error:
         err = handles[-1].error_fro(op)
         log(f"{precision}: relative Frobenius error {err:.3e}")
+    last = handles[-1]
     del handles
     stage = {k: float(np.mean([r[k] for r in reps])) for k in
              ("ms_sketch", "ms_postprocess", "ms_orth", "ms_refine", "ms_cores", "ms_nearfield", "ms_total")}
-    return dict(value=steps / elapsed, ms_step=1000.0 * elapsed / steps, stage=stage, rep=reps[0], err=err)
+    return dict(value=steps / elapsed, ms_step=1000.0 * elapsed / steps, stage=stage, rep=reps[0], err=err,
+                handle=last)
+
+
+def apply_section(S, h, reps=20):
+    """blr_apply (y = U (Atil (V* x)) + B x) on 1 and 16 vectors: time per call from
+    events on the stream, and algorithmic bytes 8 [(bk)^2 + sum_pairs m_i m_j + 2 N k + 2 N ncols]
+    against the 8 TB/s HBM peak; plus the paper's spectral error estimate (20 power
+    iterations, Section 7)."""
+    import torch
+    P, plan, g, wl = S["P"], S["plan"], S["g"], S["wl"]
+    bk = plan.b * plan.k
+    out = {}
+    for ncols in (1, 16):
+        x = P.colmajor(W.gaussian_colmajor(wl.seed, W.STREAM_POWER, g.n, ncols))
+        h.apply(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            h.apply(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = 8.0 * (bk * bk + plan.info["b_values"] + 2 * g.n * plan.k + 2 * g.n * ncols)
+        out[f"ncols_{ncols}"] = {"ms": round(ms, 4), "algorithmic_GB": round(nbytes / 1e9, 4),
+                                 "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                 "frac_of_8TBs": round(nbytes / (ms * 1e-3) / 8e12, 4)}
+    x0 = W.gaussian_colmajor(wl.seed, W.STREAM_POWER, g.n, 1)[:, 0]
+    x0 = x0 / np.linalg.norm(x0)
+    t0 = time.perf_counter()
+    e, a = h.error_power(S["op"], P.colmajor(x0), iters=20)
+    out["spectral_error"] = {"rel_err_2": e / a, "iters": 20, "s": round(time.perf_counter() - t0, 3)}
+    return out
 
 
 def cpu_baseline(S, nsample_boxes=4):
@@ -340,10 +374,17 @@ def main():
         "plan_s": round(S["plan_s"], 3),
         "roofline": roofline,
     }
+    try:
+        log("uBLR apply and spectral error")
+        out["apply"] = apply_section(S, res["handle"])
+    except Exception as e:  # extra measurement: never lose the line
+        out["apply"] = {"error": repr(e)}
+    res.pop("handle", None)
     if not args.no_mixed:
         mixed = {}
         for prec in ("bf16", "fp32"):
             m = run_mode(S, prec, args.steps, args.warmup, not args.no_error)
+            m.pop("handle", None)
             rp = m["rep"]
             st = m["stage"]
             sk = rp["sketch_flops"] / (st["ms_sketch"] * 1e-3) / 1e12

@@ -234,6 +234,7 @@ void DeviceTables::release() {
     dfree(kstep_box);
     dfree(nearm);
     dfree(colour);
+    dfree(pair_row);
 }
 
 const DeviceTables& PlanData::tables() {
@@ -267,6 +268,7 @@ const DeviceTables& PlanData::tables() {
         t->kstep_box = upload(kstep_box);
         t->nearm = upload(nearm);
         t->colour = upload(colour);
+        t->pair_row = upload(pair_row);
     } catch (...) {
         t->release();
         throw;

@@ -42,6 +42,7 @@ struct DeviceTables {
     int32_t* kstep_box = nullptr;    // [nsteps] box of each 32-row source step
     uint8_t* nearm = nullptr;        // [b*b] 1 if box j is in N_i (i-major)
     int32_t* colour = nullptr;       // [b] probe colour of each box
+    int32_t* pair_row = nullptr;     // [nnz] row box i of neighbour pair q
     void release();
 };
 
@@ -56,6 +57,7 @@ struct PlanData {
     std::vector<int64_t> b_off;
     std::vector<int32_t> kstep_ptr, kstep_box;  // 32-row source steps per box
     std::vector<uint8_t> nearm;                 // b x b neighbour mask
+    std::vector<int32_t> pair_row;              // row box of each neighbour pair
     std::vector<double> T;    // column-major b x ell (as supplied)
     std::vector<double> z;    // column-major b x ell
     std::vector<double> rho;  // [b]

@@ -1511,6 +1511,127 @@ __global__ __launch_bounds__(256) void k_apply_out(
     }
 }
 
+// Multi-vector forms of the uBLR apply (trans = 0), reading Atil and B once per
+// group of up to NC vectors.
+// part[split][row + col*bk] = sum over a column chunk of Atil(row, cc) t(cc, col), cols in group g
+template <int NC>
+__global__ __launch_bounds__(256) void k_gemv_nc(const double* __restrict__ At, int64_t ld, int64_t bk,
+                                                 const double* __restrict__ t, int ncols,
+                                                 double* __restrict__ part, int chunk) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int split = blockIdx.y, col0 = blockIdx.z * NC;
+    if (row >= bk) return;
+    const int nc = min(NC, ncols - col0);
+    const int64_t c0 = static_cast<int64_t>(split) * chunk;
+    const int64_t c1 = min(bk, c0 + chunk);
+    double acc[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+#pragma unroll 4
+    for (int64_t cc = c0; cc < c1; ++cc) {
+        const double a = At[row + cc * ld];
+#pragma unroll
+        for (int v = 0; v < NC; ++v)
+            if (v < nc) acc[v] = fma(a, t[cc + static_cast<int64_t>(col0 + v) * bk], acc[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NC; ++v)
+        if (v < nc) part[(static_cast<int64_t>(split) * ncols + col0 + v) * bk + row] = acc[v];
+}
+
+// Near-field products: npart[q*m_max + a + col*(nnz*m_max)] = sum_cc B_q(a, cc) x(J_q[cc], col)
+// for neighbour pair q = (i, j), B_q m_i x m_j column-major.  One workgroup per pair and
+// vector group.  Rows go in 64-row slices to the waves (lane = row, so every column of B_q
+// is read coalesced); when a 256-row block has fewer than four slices the waves of a slice
+// split its columns and their partial sums meet in LDS.
+template <int NC>
+__global__ __launch_bounds__(256) void k_bsp_n(const int64_t* __restrict__ box_ptr,
+                                               const int32_t* __restrict__ near_idx,
+                                               const int32_t* __restrict__ pair_row,
+                                               const int64_t* __restrict__ b_off,
+                                               const double* __restrict__ Bv, int m_max,
+                                               int64_t nnz, const double* __restrict__ x,
+                                               int64_t ldx, int ncols, double* __restrict__ npart) {
+    __shared__ double red[NC * 256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = blockIdx.x, col0 = blockIdx.y * NC;
+    const int nc = min(NC, ncols - col0);
+    const int i = pair_row[q], j = near_idx[q];
+    const int64_t i0 = box_ptr[i], j0 = box_ptr[j];
+    const int mi = static_cast<int>(box_ptr[i + 1] - i0);
+    const int mj = static_cast<int>(box_ptr[j + 1] - j0);
+    const double* B = Bv + b_off[q];
+    const double* xj[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) xj[v] = x + j0 + static_cast<int64_t>(col0 + min(v, nc - 1)) * ldx;
+    for (int a0 = 0; a0 < mi; a0 += 256) {
+        const int slices = min(4, (mi - a0 + 63) / 64);
+        const int F = slices == 1 ? 4 : (slices == 2 ? 2 : 1);   // waves per slice
+        const int slice = wave / F, part = wave - slice * F;
+        const int a = a0 + slice * 64 + lane;
+        const int cq = (mj + F - 1) / F;
+        const int cbeg = part * cq, cend = slice < slices ? min(mj, cbeg + cq) : cbeg;
+        const int arow = a < mi ? a : mi - 1;                    // clamped row for the loads
+        double acc[NC];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+#pragma unroll 4
+        for (int cc = cbeg; cc < cend; ++cc) {
+            const double bval = B[arow + static_cast<int64_t>(cc) * mi];
+#pragma unroll
+            for (int v = 0; v < NC; ++v) acc[v] = fma(bval, xj[v][cc], acc[v]);
+        }
+        if (F > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < NC; ++v) red[v * 256 + tid] = acc[v];
+            __syncthreads();
+            if (part == 0) {
+                for (int p = 1; p < F; ++p)
+#pragma unroll
+                    for (int v = 0; v < NC; ++v) acc[v] += red[v * 256 + tid + 64 * p];
+            }
+        }
+        if (part == 0 && slice < slices && a < mi) {
+#pragma unroll
+            for (int v = 0; v < NC; ++v)
+                if (v < nc) npart[static_cast<int64_t>(q) * m_max + a + static_cast<int64_t>(col0 + v) * nnz * m_max] = acc[v];
+        }
+    }
+}
+
+// y(I_i, col) = U_i t(i-block, col) + sum over the neighbour pairs q of i of npart(q, :, col)
+template <int NC>
+__global__ __launch_bounds__(256) void k_apply_out_n(const double* __restrict__ S, int64_t ldS,
+                                                     const int64_t* __restrict__ box_ptr, int k,
+                                                     const double* __restrict__ t, int64_t bk,
+                                                     const int32_t* __restrict__ near_ptr, int m_max,
+                                                     int64_t nnz, const double* __restrict__ npart,
+                                                     int ncols, double* __restrict__ y, int64_t ldy) {
+    const int i = blockIdx.x, col0 = blockIdx.y * NC;
+    const int nc = min(NC, ncols - col0);
+    const int64_t r0 = box_ptr[i];
+    const int m = static_cast<int>(box_ptr[i + 1] - r0);
+    for (int a = threadIdx.x; a < m; a += 256) {
+        double acc[NC];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+        for (int s2 = 0; s2 < k; ++s2) {
+            const double u = S[r0 + a + static_cast<int64_t>(s2) * ldS];
+#pragma unroll
+            for (int v = 0; v < NC; ++v)
+                if (v < nc) acc[v] = fma(u, t[static_cast<int64_t>(i) * k + s2 + static_cast<int64_t>(col0 + v) * bk], acc[v]);
+        }
+        for (int q = near_ptr[i]; q < near_ptr[i + 1]; ++q)
+#pragma unroll
+            for (int v = 0; v < NC; ++v)
+                if (v < nc) acc[v] += npart[static_cast<int64_t>(q) * m_max + a + static_cast<int64_t>(col0 + v) * nnz * m_max];
+#pragma unroll
+        for (int v = 0; v < NC; ++v)
+            if (v < nc) y[r0 + a + static_cast<int64_t>(col0 + v) * ldy] = acc[v];
+    }
+}
+
 // ------------------------------------------------------------ exact error
 template <class AS>
 __global__ __launch_bounds__(256) void k_err_fro(AS A, const int64_t* __restrict__ box_ptr,
@@ -1797,7 +1918,7 @@ static int apply_nsplit(int64_t bk) { return static_cast<int>(std::min<int64_t>(
 
 int64_t apply_workspace_doubles(const PlanData& P, int64_t ncols) {
     const int64_t bk = static_cast<int64_t>(P.b) * P.k;
-    return (2 + apply_nsplit(bk)) * bk * ncols;
+    return (2 + apply_nsplit(bk)) * bk * ncols + P.near_nnz * P.m_max * ncols;
 }
 
 void launch_ublr_apply(const PlanData& P, const DeviceTables& t, const double* U, const double* V,
@@ -1813,12 +1934,31 @@ void launch_ublr_apply(const PlanData& P, const DeviceTables& t, const double* U
     hipLaunchKernelGGL(k_apply_proj, dim3(P.b, ncols), dim3(256), 0, s, Sin, P.n, t.box_ptr, P.k,
                        x, ldx, t1, bk);
     if (!trans) {
+        // Atil and B are read once per group of NC vectors
         const int nsplit = apply_nsplit(bk);
         const int chunk = static_cast<int>((bk + nsplit - 1) / nsplit);
-        hipLaunchKernelGGL(k_gemv_n, dim3((bk + 255) / 256, nsplit, ncols), dim3(256), 0, s, Atil,
-                           bk, bk, t1, part, chunk);
-        hipLaunchKernelGGL(k_sum_parts, dim3((bk * ncols + 255) / 256), dim3(256), 0, s, part,
-                           nsplit, bk * ncols, t2);
+        double* npart = part + nsplit * bk * ncols;
+        const int nc = ncols >= 16 ? 16 : ncols >= 8 ? 8 : ncols >= 4 ? 4 : (ncols >= 2 ? 2 : 1);
+        const unsigned groups = static_cast<unsigned>((ncols + nc - 1) / nc);
+        auto run = [&](auto ncv) {
+            constexpr int NC = decltype(ncv)::value;
+            hipLaunchKernelGGL((k_gemv_nc<NC>), dim3((bk + 255) / 256, nsplit, groups), dim3(256), 0, s, Atil,
+                               bk, bk, t1, static_cast<int>(ncols), part, chunk);
+            hipLaunchKernelGGL(k_sum_parts, dim3((bk * ncols + 255) / 256), dim3(256), 0, s, part,
+                               nsplit, bk * ncols, t2);
+            hipLaunchKernelGGL((k_bsp_n<NC>), dim3(static_cast<unsigned>(P.near_nnz), groups), dim3(256), 0, s,
+                               t.box_ptr, t.near_idx, t.pair_row, t.b_off, Bv, P.m_max,
+                               P.near_nnz, x, ldx, static_cast<int>(ncols), npart);
+            hipLaunchKernelGGL((k_apply_out_n<NC>), dim3(P.b, groups), dim3(256), 0, s, Sout, P.n, t.box_ptr,
+                               P.k, t2, bk, t.near_ptr, P.m_max, P.near_nnz, npart, static_cast<int>(ncols), y, ldy);
+        };
+        if (nc == 16) run(std::integral_constant<int, 16>{});
+        else if (nc == 8) run(std::integral_constant<int, 8>{});
+        else if (nc == 4) run(std::integral_constant<int, 4>{});
+        else if (nc == 2) run(std::integral_constant<int, 2>{});
+        else run(std::integral_constant<int, 1>{});
+        check_launch("uBLR apply");
+        return;
     } else {
         hipLaunchKernelGGL(k_gemv_t, dim3((bk + 3) / 4, ncols), dim3(256), 0, s, Atil, bk, bk, t1, t2);
     }

@@ -475,6 +475,9 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
     P->kstep_box.resize(P->kstep_ptr[b]);
     for (int i = 0; i < b; ++i)
         for (int q = P->kstep_ptr[i]; q < P->kstep_ptr[i + 1]; ++q) P->kstep_box[q] = i;
+    P->pair_row.resize(P->near_nnz);
+    for (int i = 0; i < b; ++i)
+        for (int q = P->near_ptr[i]; q < P->near_ptr[i + 1]; ++q) P->pair_row[q] = i;
     // neighbour mask for the far-field refinement sketch
     P->nearm.assign(static_cast<size_t>(b) * b, 0);
     for (int i = 0; i < b; ++i)

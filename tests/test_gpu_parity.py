@@ -51,13 +51,17 @@ def _case(name):
     if name == "exp_n2500":
         g = W.grid_geometry(2, 5, 10, jitter=0.25, seed=7)
         return dict(name=name, g=g, k=16, p=10, kind="exp", seed=20250104)
+    if name == "log_boxes306":          # boxes of more than 256 points
+        g = W.grid_geometry(2, 4, (18, 17), jitter=0.2, seed=11)
+        return dict(name=name, g=g, k=16, p=10, kind="log", seed=20250106)
     if name == "cos_uneven":
         g = W.irregular_grid_geometry([[9, 12, 10, 14, 11, 9], [10, 13, 9, 12, 11]], jitter=0.2, seed=9)
         return dict(name=name, g=g, k=20, p=10, kind="cos", seed=20250105)
     raise KeyError(name)
 
 
-CASES = ["planted", "laplace_n9216", "laplace_ragged_jitter", "invr3d_n8000", "exp_n2500", "cos_uneven"]
+CASES = ["planted", "laplace_n9216", "laplace_ragged_jitter", "invr3d_n8000", "exp_n2500", "cos_uneven",
+         "log_boxes306"]
 
 
 def _oracle(c):
@@ -182,13 +186,14 @@ def test_error_band(run):
 def test_apply_parity(run):
     g, k = run["c"]["g"], run["c"]["k"]
     P = run["P"]
-    x = np.random.default_rng(3).standard_normal((g.n, 3))
-    xd = P.colmajor(x)
     res = run["res"]
-    for trans in (False, True):
-        y = _np(run["h"].apply(xd, trans=trans))
-        yo = O.ublr_apply(res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k, x, trans=trans)
-        _close(y, yo, 1e-10)
+    for ncols in (1, 3, 21):          # vector groups of 1, 2 + 1, 16 + 4 + 1
+        x = np.random.default_rng(3 + ncols).standard_normal((g.n, ncols))
+        xd = P.colmajor(x)
+        for trans in (False, True):
+            y = _np(run["h"].apply(xd, trans=trans))
+            yo = O.ublr_apply(res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k, x, trans=trans)
+            _close(y, yo, 1e-10)
 
 
 def test_operator_apply_parity(run):
