@@ -115,27 +115,28 @@ def run_mode(S, precision, steps, warmup, with_error):
 
 
 def apply_section(S, h, reps=20):
-    """blr_apply (y = U (Atil (V* x)) + B x) on 1 and 16 vectors: time per call from
-    events on the stream, and algorithmic bytes 8 [(bk)^2 + sum_pairs m_i m_j + 2 N k + 2 N ncols]
+    """blr_apply (y = U (Atil (V* x)) + B x) on 1 and 16 vectors, and its transpose on one
+    vector: time per call from events on the stream, and algorithmic bytes
+    8 [(bk)^2 + sum_pairs m_i m_j + 2 N k + 2 N ncols]
     against the 8 TB/s HBM peak; plus the paper's spectral error estimate (20 power
     iterations, Section 7)."""
     import torch
     P, plan, g, wl = S["P"], S["plan"], S["g"], S["wl"]
     bk = plan.b * plan.k
     out = {}
-    for ncols in (1, 16):
+    for ncols, trans in ((1, False), (16, False), (1, True)):
         x = P.colmajor(W.gaussian_colmajor(wl.seed, W.STREAM_POWER, g.n, ncols))
-        h.apply(x)
+        h.apply(x, trans=trans)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            h.apply(x)
+            h.apply(x, trans=trans)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         nbytes = 8.0 * (bk * bk + plan.info["b_values"] + 2 * g.n * plan.k + 2 * g.n * ncols)
-        out[f"ncols_{ncols}"] = {"ms": round(ms, 4), "algorithmic_GB": round(nbytes / 1e9, 4),
+        out[f"ncols_{ncols}" + ("_trans" if trans else "")] = {"ms": round(ms, 4), "algorithmic_GB": round(nbytes / 1e9, 4),
                                  "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                                  "frac_of_8TBs": round(nbytes / (ms * 1e-3) / 8e12, 4)}
     x0 = W.gaussian_colmajor(wl.seed, W.STREAM_POWER, g.n, 1)[:, 0]

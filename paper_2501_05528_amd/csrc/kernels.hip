@@ -4,7 +4,8 @@
 // (v_mfma_f64_16x16x4f64) with the A operand generated tile by tile into LDS
 // (kernel matrices: from the point coordinates; dense operators: read in
 // place).  Post-processing, probes, apply and error evaluation are
-// bandwidth- or generation-bound and use plain VALU code.
+// bandwidth- or generation-bound and use plain VALU code (the near-field apply
+// on 16 vectors at a time takes MFMA as well).
 //
 // MFMA f64 16x16x4 operand layout (wave64, lane l):
 //   A (16x4):  lane l holds A[l % 16][l / 16]
@@ -1420,48 +1421,21 @@ __global__ __launch_bounds__(256) void k_nf_b(
     }
 }
 
-// ------------------------------------------------------------ uBLR apply
-// t[(j*k + a) + col*bk] = sum_{row in I_j} S(row, a) x(row, col); one workgroup
-// per (box, column), one wave per basis column.
-__global__ __launch_bounds__(256) void k_apply_proj(const double* __restrict__ S, int64_t ldS,
-                                                    const int64_t* __restrict__ box_ptr, int k,
-                                                    const double* __restrict__ x, int64_t ldx,
-                                                    double* __restrict__ t, int64_t bk) {
-    const int j = blockIdx.x, col = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t r0 = box_ptr[j];
-    const int m = static_cast<int>(box_ptr[j + 1] - r0);
-    const double* xc = x + static_cast<int64_t>(col) * ldx;
-    for (int a = wave; a < k; a += 4) {
-        double acc = 0.0;
-        for (int q = lane; q < m; q += 64) acc += S[r0 + q + static_cast<int64_t>(a) * ldS] * xc[r0 + q];
-        acc = wave_sum(acc);
-        if (lane == 0) t[static_cast<int64_t>(j) * k + a + static_cast<int64_t>(col) * bk] = acc;
-    }
-}
-
-// part[split][row + col*bk] = sum over a column chunk of Atil(row, cc) t(cc, col)
-__global__ __launch_bounds__(256) void k_gemv_n(const double* __restrict__ At, int64_t ld,
-                                                int64_t bk, const double* __restrict__ t,
-                                                double* __restrict__ part, int chunk) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int split = blockIdx.y, col = blockIdx.z;
-    if (row >= bk) return;
-    const int64_t c0 = static_cast<int64_t>(split) * chunk;
-    const int64_t c1 = min(bk, c0 + chunk);
-    const double* tc = t + static_cast<int64_t>(col) * bk;
-    double acc = 0.0;
-    for (int64_t cc = c0; cc < c1; ++cc) acc += At[row + cc * ld] * tc[cc];
-    part[(static_cast<int64_t>(split) * gridDim.z + col) * bk + row] = acc;
-}
-
+// out[idx] = sum_s part[s len + idx]: 64 outputs per workgroup; the four waves take every
+// fourth split and their sums meet in LDS.
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nsplit,
                                                    int64_t len, double* __restrict__ out) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (idx >= len) return;
+    __shared__ double red[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 64 + lane;
     double acc = 0.0;
-    for (int s = 0; s < nsplit; ++s) acc += part[static_cast<int64_t>(s) * len + idx];
-    out[idx] = acc;
+    if (idx < len) {
+#pragma unroll 8
+        for (int s2 = wave; s2 < nsplit; s2 += 4) acc += part[static_cast<int64_t>(s2) * len + idx];
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (wave == 0 && idx < len) out[idx] = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
 }
 
 // out(col_idx, col) = sum_row Atil(row, col_idx) t(row, col): one wave per output
@@ -1480,155 +1454,292 @@ __global__ __launch_bounds__(256) void k_gemv_t(const double* __restrict__ At, i
     if (lane == 0) out[c + static_cast<int64_t>(col) * bk] = acc;
 }
 
-// y(I_i, col) = S_i t(i-block, col) + near-field part; S = U (trans 0) or V (trans 1)
-__global__ __launch_bounds__(256) void k_apply_out(
-    const double* __restrict__ S, int64_t ldS, const int64_t* __restrict__ box_ptr, int k,
-    const double* __restrict__ t, int64_t bk, const int32_t* __restrict__ near_ptr,
-    const int32_t* __restrict__ near_idx, const int32_t* __restrict__ near_tpos,
-    const int64_t* __restrict__ b_off, const double* __restrict__ Bv, int trans,
-    const double* __restrict__ x, int64_t ldx, double* __restrict__ y, int64_t ldy) {
-    const int i = blockIdx.x, col = blockIdx.y;
-    const int64_t r0 = box_ptr[i];
-    const int m = static_cast<int>(box_ptr[i + 1] - r0);
-    const double* tc = t + static_cast<int64_t>(col) * bk + static_cast<int64_t>(i) * k;
-    const double* xc = x + static_cast<int64_t>(col) * ldx;
-    for (int a = threadIdx.x; a < m; a += 256) {
-        double acc = 0.0;
-        for (int s = 0; s < k; ++s) acc += S[r0 + a + static_cast<int64_t>(s) * ldS] * tc[s];
-        for (int q = near_ptr[i]; q < near_ptr[i + 1]; ++q) {
-            const int j = near_idx[q];
-            const int64_t j0 = box_ptr[j];
-            const int mj = static_cast<int>(box_ptr[j + 1] - j0);
-            if (!trans) {
-                const double* blk = Bv + b_off[q];  // B_ij, m x mj
-                for (int cc = 0; cc < mj; ++cc) acc += blk[a + static_cast<int64_t>(cc) * m] * xc[j0 + cc];
-            } else {
-                const double* blk = Bv + b_off[near_tpos[q]];  // B_ji, mj x m
-                for (int cc = 0; cc < mj; ++cc) acc += blk[cc + static_cast<int64_t>(a) * mj] * xc[j0 + cc];
+
+// Multi-vector forms of the uBLR apply.  Vectors go in groups of NC; each kernel stages the
+// small per-group operand (t or x) in LDS so every value of Atil, B, U or V read from HBM
+// serves all NC vectors.
+
+// t(j k + s, col) = sum_a S(I_j[a], s) x(I_j[a], col): one workgroup per (box j, vector
+// group); rows of S_j and x_j staged in 32-row chunks, thread o owns outputs o + 256 u.
+template <int NC>
+__global__ __launch_bounds__(256) void k_proj_nc(const double* __restrict__ S, int64_t ldS,
+                                                 const int64_t* __restrict__ box_ptr, int k,
+                                                 const double* __restrict__ x, int64_t ldx, int ncols,
+                                                 double* __restrict__ t, int64_t bk) {
+    constexpr int RC = 32, SP = 65;
+    __shared__ double sS[RC * SP];
+    __shared__ double sX[RC * NC];
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x, col0 = blockIdx.y * NC;
+    const int nc = min(NC, ncols - col0);
+    const int64_t r0 = box_ptr[j];
+    const int m = static_cast<int>(box_ptr[j + 1] - r0);
+    const int nout = k * NC;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int a0 = 0; a0 < m; a0 += RC) {
+        const int rows = min(RC, m - a0);
+        __syncthreads();
+        for (int e = tid; e < RC * k; e += 256) {
+            const int rr = e % RC, s2 = e / RC;
+            sS[rr * SP + s2] = rr < rows ? S[r0 + a0 + rr + static_cast<int64_t>(s2) * ldS] : 0.0;
+        }
+        for (int e = tid; e < RC * NC; e += 256) {
+            const int rr = e % RC, v = e / RC;
+            sX[rr * NC + v] = (rr < rows && v < nc) ? x[r0 + a0 + rr + static_cast<int64_t>(col0 + v) * ldx] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int o = tid + 256 * u;
+            if (o < nout) {
+                const int s2 = o % k, v = o / k;
+#pragma unroll 8
+                for (int rr = 0; rr < RC; ++rr) acc[u] = fma(sS[rr * SP + s2], sX[rr * NC + v], acc[u]);
             }
         }
-        y[r0 + a + static_cast<int64_t>(col) * ldy] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int o = tid + 256 * u;
+        if (o < nout) {
+            const int s2 = o % k, v = o / k;
+            if (v < nc) t[static_cast<int64_t>(j) * k + s2 + static_cast<int64_t>(col0 + v) * bk] = acc[u];
+        }
     }
 }
 
-// Multi-vector forms of the uBLR apply (trans = 0), reading Atil and B once per
-// group of up to NC vectors.
-// part[split][row + col*bk] = sum over a column chunk of Atil(row, cc) t(cc, col), cols in group g
+// part[split][row + col*bk] = sum over one column chunk of Atil(row, cc) t(cc, col) for the
+// vectors of group blockIdx.z.  Each thread owns rows row0 and row0 + 256 of a 512-row block;
+// the chunk of t (chunk x NC <= 4096 values) sits in dynamic LDS.
 template <int NC>
 __global__ __launch_bounds__(256) void k_gemv_nc(const double* __restrict__ At, int64_t ld, int64_t bk,
                                                  const double* __restrict__ t, int ncols,
                                                  double* __restrict__ part, int chunk) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    extern __shared__ double st[];                      // chunk x NC values
+    const int tid = threadIdx.x;
     const int split = blockIdx.y, col0 = blockIdx.z * NC;
-    if (row >= bk) return;
     const int nc = min(NC, ncols - col0);
     const int64_t c0 = static_cast<int64_t>(split) * chunk;
-    const int64_t c1 = min(bk, c0 + chunk);
+    const int len = static_cast<int>(max<int64_t>(0, min<int64_t>(bk - c0, chunk)));
+    for (int e = tid; e < len * NC; e += 256) {
+        const int cc = e % len, v = e / len;
+        st[cc * NC + v] = v < nc ? t[c0 + cc + static_cast<int64_t>(col0 + v) * bk] : 0.0;
+    }
+    __syncthreads();
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 512 + tid;
+    const int64_t row1 = row0 + 256;
+    const int64_t ra = row0 < bk ? row0 : bk - 1, rb = row1 < bk ? row1 : bk - 1;
+    const double* a = At + c0 * ld;
+    double acc0[NC], acc1[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) acc0[v] = acc1[v] = 0.0;
+#pragma unroll 4
+    for (int cc = 0; cc < len; ++cc) {
+        const double x0 = a[ra + static_cast<int64_t>(cc) * ld];
+        const double x1 = a[rb + static_cast<int64_t>(cc) * ld];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) {
+            const double tv = st[cc * NC + v];
+            acc0[v] = fma(x0, tv, acc0[v]);
+            acc1[v] = fma(x1, tv, acc1[v]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+        if (v >= nc) continue;
+        double* out = part + (static_cast<int64_t>(split) * ncols + col0 + v) * bk;
+        if (row0 < bk) out[row0] = acc0[v];
+        if (row1 < bk) out[row1] = acc1[v];
+    }
+}
+
+// y(I_i, col) = U_i t(i-block, col) + sum over the neighbours j of i of B_ij x(I_j, col).
+// One workgroup per (box i, vector group, 64-row slice of I_i); lane = row, so each column of
+// U_i and B_ij is read as one coalesced 512-byte segment.  The terms (U_i first, then the
+// neighbours in list order) go through LDS in chunks of up to 256 columns whose x values are
+// staged there; the four waves split each chunk's columns and their sums meet in LDS.
+template <int NC>
+__global__ __launch_bounds__(256) void k_near_out_n(const double* __restrict__ U, int64_t ldU,
+                                                    const int64_t* __restrict__ box_ptr, int k,
+                                                    const double* __restrict__ t2, int64_t bk,
+                                                    const int32_t* __restrict__ near_ptr,
+                                                    const int32_t* __restrict__ near_idx,
+                                                    const int64_t* __restrict__ b_off,
+                                                    const double* __restrict__ Bv,
+                                                    const double* __restrict__ x, int64_t ldx, int ncols,
+                                                    double* __restrict__ y, int64_t ldy) {
+    constexpr int CH = 256, SP = NC == 1 ? 1 : NC + 1;   // padded rows: conflict-free staging
+    __shared__ double sx[CH * SP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = blockIdx.x, col0 = blockIdx.y * NC, slice = blockIdx.z;
+    const int nc = min(NC, ncols - col0);
+    const int64_t r0 = box_ptr[i];
+    const int mi = static_cast<int>(box_ptr[i + 1] - r0);
+    if (slice * 64 >= mi) return;                      // uniform over the workgroup
+    const int a = slice * 64 + lane;
+    const int arow = a < mi ? a : mi - 1;              // clamped row for the loads
     double acc[NC];
 #pragma unroll
     for (int v = 0; v < NC; ++v) acc[v] = 0.0;
-#pragma unroll 4
-    for (int64_t cc = c0; cc < c1; ++cc) {
-        const double a = At[row + cc * ld];
-#pragma unroll
-        for (int v = 0; v < NC; ++v)
-            if (v < nc) acc[v] = fma(a, t[cc + static_cast<int64_t>(col0 + v) * bk], acc[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NC; ++v)
-        if (v < nc) part[(static_cast<int64_t>(split) * ncols + col0 + v) * bk + row] = acc[v];
-}
-
-// Near-field products: npart[q*m_max + a + col*(nnz*m_max)] = sum_cc B_q(a, cc) x(J_q[cc], col)
-// for neighbour pair q = (i, j), B_q m_i x m_j column-major.  One workgroup per pair and
-// vector group.  Rows go in 64-row slices to the waves (lane = row, so every column of B_q
-// is read coalesced); when a 256-row block has fewer than four slices the waves of a slice
-// split its columns and their partial sums meet in LDS.
-template <int NC>
-__global__ __launch_bounds__(256) void k_bsp_n(const int64_t* __restrict__ box_ptr,
-                                               const int32_t* __restrict__ near_idx,
-                                               const int32_t* __restrict__ pair_row,
-                                               const int64_t* __restrict__ b_off,
-                                               const double* __restrict__ Bv, int m_max,
-                                               int64_t nnz, const double* __restrict__ x,
-                                               int64_t ldx, int ncols, double* __restrict__ npart) {
-    __shared__ double red[NC * 256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q = blockIdx.x, col0 = blockIdx.y * NC;
-    const int nc = min(NC, ncols - col0);
-    const int i = pair_row[q], j = near_idx[q];
-    const int64_t i0 = box_ptr[i], j0 = box_ptr[j];
-    const int mi = static_cast<int>(box_ptr[i + 1] - i0);
-    const int mj = static_cast<int>(box_ptr[j + 1] - j0);
-    const double* B = Bv + b_off[q];
-    const double* xj[NC];
-#pragma unroll
-    for (int v = 0; v < NC; ++v) xj[v] = x + j0 + static_cast<int64_t>(col0 + min(v, nc - 1)) * ldx;
-    for (int a0 = 0; a0 < mi; a0 += 256) {
-        const int slices = min(4, (mi - a0 + 63) / 64);
-        const int F = slices == 1 ? 4 : (slices == 2 ? 2 : 1);   // waves per slice
-        const int slice = wave / F, part = wave - slice * F;
-        const int a = a0 + slice * 64 + lane;
-        const int cq = (mj + F - 1) / F;
-        const int cbeg = part * cq, cend = slice < slices ? min(mj, cbeg + cq) : cbeg;
-        const int arow = a < mi ? a : mi - 1;                    // clamped row for the loads
-        double acc[NC];
-#pragma unroll
-        for (int v = 0; v < NC; ++v) acc[v] = 0.0;
-#pragma unroll 4
-        for (int cc = cbeg; cc < cend; ++cc) {
-            const double bval = B[arow + static_cast<int64_t>(cc) * mi];
-#pragma unroll
-            for (int v = 0; v < NC; ++v) acc[v] = fma(bval, xj[v][cc], acc[v]);
+    const int q0 = near_ptr[i], q1 = near_ptr[i + 1];
+    for (int item = q0 - 1; item < q1; ++item) {
+        const double* M;
+        const double* xs;
+        int64_t ldm, ldxs;
+        int len;
+        if (item < q0) {
+            M = U + r0;
+            ldm = ldU;
+            len = k;
+            xs = t2 + static_cast<int64_t>(i) * k;
+            ldxs = bk;
+        } else {
+            const int j = near_idx[item];
+            const int64_t j0 = box_ptr[j];
+            M = Bv + b_off[item];
+            ldm = mi;
+            len = static_cast<int>(box_ptr[j + 1] - j0);
+            xs = x + j0;
+            ldxs = ldx;
         }
-        if (F > 1) {
+        for (int c0 = 0; c0 < len; c0 += CH) {
+            const int cl = min(CH, len - c0);
             __syncthreads();
+            if (tid < cl) {
 #pragma unroll
-            for (int v = 0; v < NC; ++v) red[v * 256 + tid] = acc[v];
+                for (int v = 0; v < NC; ++v)
+                    sx[tid * SP + v] = v < nc ? xs[c0 + tid + static_cast<int64_t>(col0 + v) * ldxs] : 0.0;
+            }
             __syncthreads();
-            if (part == 0) {
-                for (int p = 1; p < F; ++p)
+            const int cq = (cl + 3) / 4;
+            const int cb = wave * cq, ce = min(cl, cb + cq);
+            const double* pm = M + static_cast<int64_t>(c0 + cb) * ldm + arow;
+#pragma unroll 4
+            for (int cc = cb; cc < ce; ++cc, pm += ldm) {
+                const double bval = *pm;
 #pragma unroll
-                    for (int v = 0; v < NC; ++v) acc[v] += red[v * 256 + tid + 64 * p];
+                for (int v = 0; v < NC; ++v) acc[v] = fma(bval, sx[cc * SP + v], acc[v]);
             }
         }
-        if (part == 0 && slice < slices && a < mi) {
+    }
+    __syncthreads();
 #pragma unroll
-            for (int v = 0; v < NC; ++v)
-                if (v < nc) npart[static_cast<int64_t>(q) * m_max + a + static_cast<int64_t>(col0 + v) * nnz * m_max] = acc[v];
-        }
+    for (int v = 0; v < NC; ++v) sx[v * 256 + tid] = acc[v];
+    __syncthreads();
+    if (wave == 0 && a < mi) {
+#pragma unroll
+        for (int v = 0; v < NC; ++v)
+            if (v < nc)
+                y[r0 + a + static_cast<int64_t>(col0 + v) * ldy] =
+                    sx[v * 256 + lane] + sx[v * 256 + 64 + lane] + sx[v * 256 + 128 + lane] + sx[v * 256 + 192 + lane];
     }
 }
 
-// y(I_i, col) = U_i t(i-block, col) + sum over the neighbour pairs q of i of npart(q, :, col)
-template <int NC>
-__global__ __launch_bounds__(256) void k_apply_out_n(const double* __restrict__ S, int64_t ldS,
-                                                     const int64_t* __restrict__ box_ptr, int k,
-                                                     const double* __restrict__ t, int64_t bk,
-                                                     const int32_t* __restrict__ near_ptr, int m_max,
-                                                     int64_t nnz, const double* __restrict__ npart,
-                                                     int ncols, double* __restrict__ y, int64_t ldy) {
-    const int i = blockIdx.x, col0 = blockIdx.y * NC;
+// Output stage of the apply for a group of 16 vectors, on FP64 MFMA.  Output box o = blockIdx.x,
+// 64-row slice blockIdx.z; wave w owns output rows 16 w .. 16 w + 15 of the slice and all
+// columns of every term, so no partial sums cross waves.
+//   trans = 0: y(I_o) = U_o t2(o-block) + sum_{j in N(o)} B_oj x(I_j)
+//   trans = 1: y(I_o) = V_o t2(o-block) + sum_{i in N(o)} B_io^T x(I_i)
+// A term is a matrix M whose element (output row r, inner index c) sits at M[r rs + c ks]
+// (rs = 1 for U, V and B_oj; rs = m_i, ks = 1 for B_io^T).  A operand = M's 16 x 4 block
+// (lane l: row l % 16, inner index l / 16), B operand = the staged x rows (4 x 16), zero
+// beyond the term's inner length.
+template <int TRANS>
+__global__ __launch_bounds__(256) void k_near_m16(const double* __restrict__ S, int64_t ldS,
+                                                  const int64_t* __restrict__ box_ptr, int k,
+                                                  const double* __restrict__ t2, int64_t bk,
+                                                  const int32_t* __restrict__ near_ptr,
+                                                  const int32_t* __restrict__ near_idx,
+                                                  const int32_t* __restrict__ near_tpos,
+                                                  const int64_t* __restrict__ b_off,
+                                                  const double* __restrict__ Bv,
+                                                  const double* __restrict__ x, int64_t ldx, int ncols,
+                                                  double* __restrict__ y, int64_t ldy) {
+    constexpr int CH = 128, NC = 16, SP = NC + 1;     // padded rows: conflict-free staging
+    __shared__ double sx[CH * SP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int o = blockIdx.x, col0 = blockIdx.y * NC, slice = blockIdx.z;
     const int nc = min(NC, ncols - col0);
-    const int64_t r0 = box_ptr[i];
-    const int m = static_cast<int>(box_ptr[i + 1] - r0);
-    for (int a = threadIdx.x; a < m; a += 256) {
-        double acc[NC];
-#pragma unroll
-        for (int v = 0; v < NC; ++v) acc[v] = 0.0;
-        for (int s2 = 0; s2 < k; ++s2) {
-            const double u = S[r0 + a + static_cast<int64_t>(s2) * ldS];
-#pragma unroll
-            for (int v = 0; v < NC; ++v)
-                if (v < nc) acc[v] = fma(u, t[static_cast<int64_t>(i) * k + s2 + static_cast<int64_t>(col0 + v) * bk], acc[v]);
+    const int64_t r0 = box_ptr[o];
+    const int mo = static_cast<int>(box_ptr[o + 1] - r0);
+    if (slice * 64 >= mo) return;                      // uniform over the workgroup
+    const int arow_l = slice * 64 + wave * 16 + (lane & 15);
+    const int arow = arow_l < mo ? arow_l : mo - 1;    // rows past the box: clamped, never written
+    const int kq = lane >> 4, col = lane & 15;
+    d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+    const int q0 = near_ptr[o], q1 = near_ptr[o + 1];
+    for (int item = q0 - 1; item < q1; ++item) {
+        const double* M;
+        const double* xs;
+        int64_t rs, ks, ldxs;
+        int len;
+        if (item < q0) {
+            M = S + r0;
+            rs = 1;
+            ks = ldS;
+            len = k;
+            xs = t2 + static_cast<int64_t>(o) * k;
+            ldxs = bk;
+        } else {
+            const int j = near_idx[item];
+            const int64_t j0 = box_ptr[j];
+            const int mj = static_cast<int>(box_ptr[j + 1] - j0);
+            if (TRANS) {
+                M = Bv + b_off[near_tpos[item]];       // B_jo, m_j x m_o
+                rs = mj;
+                ks = 1;
+            } else {
+                M = Bv + b_off[item];                  // B_oj, m_o x m_j
+                rs = 1;
+                ks = mo;
+            }
+            len = mj;
+            xs = x + j0;
+            ldxs = ldx;
         }
-        for (int q = near_ptr[i]; q < near_ptr[i + 1]; ++q)
+        const double* Mr = M + static_cast<int64_t>(arow) * rs;
+        for (int c0 = 0; c0 < len; c0 += CH) {
+            const int cl = min(CH, len - c0);
+            const int cl4 = (cl + 3) & ~3;
+            __syncthreads();
+            {
+                const int cc = tid & (CH - 1);
+                if (cc < cl4)
+                    for (int v = tid >> 7; v < NC; v += 2)
+                        sx[cc * SP + v] = (cc < cl && v < nc) ? xs[c0 + cc + static_cast<int64_t>(col0 + v) * ldxs] : 0.0;
+            }
+            __syncthreads();
+            // Eight loads are issued before their MFMAs (two accumulators, steps alternating).
+            // Inner indices past the term read a clamped in-range entry; their staged x rows are zero.
+            const int64_t step4 = 4 * ks;
+            const double* pa = Mr + static_cast<int64_t>(c0 + kq) * ks;
+            int cc = 0;
+            for (; cc + 32 <= cl; cc += 32) {
+                double av[8];
 #pragma unroll
-            for (int v = 0; v < NC; ++v)
-                if (v < nc) acc[v] += npart[static_cast<int64_t>(q) * m_max + a + static_cast<int64_t>(col0 + v) * nnz * m_max];
+                for (int u = 0; u < 8; ++u) av[u] = pa[u * step4];
 #pragma unroll
-        for (int v = 0; v < NC; ++v)
-            if (v < nc) y[r0 + a + static_cast<int64_t>(col0 + v) * ldy] = acc[v];
+                for (int u = 0; u < 8; u += 2) {
+                    acc = mfma64(av[u], sx[(cc + 4 * u + kq) * SP + col], acc);
+                    acc2 = mfma64(av[u + 1], sx[(cc + 4 * u + 4 + kq) * SP + col], acc2);
+                }
+                pa += 8 * step4;
+            }
+            for (; cc + 4 <= cl; cc += 4, pa += step4) acc = mfma64(pa[0], sx[(cc + kq) * SP + col], acc);
+            if (cc < cl4) {
+                const int c = cc + kq;
+                const double av = Mr[static_cast<int64_t>(c0 + (c < cl ? c : cl - 1)) * ks];
+                acc = mfma64(av, sx[c * SP + col], acc);
+            }
+        }
+    }
+    const int dcol = d_col(lane);
+    if (dcol < nc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = slice * 64 + wave * 16 + d_row(lane, v);
+            if (a < mo) y[r0 + a + static_cast<int64_t>(col0 + dcol) * ldy] = acc[v] + acc2[v];
+        }
     }
 }
 
@@ -1914,56 +2025,81 @@ void launch_nf_q(const PlanData& P, const DeviceTables& t, const double* V, cons
     check_launch("near field (Q)");
 }
 
-static int apply_nsplit(int64_t bk) { return static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, bk / 256))); }
+// Vector group width and column split of Atil for an apply on ncols vectors: the split gives
+// about 2048 workgroups, keeps the partial sums under 1/8 of Atil's bytes and a chunk of t
+// within the 4096 LDS values of k_gemv_nc.
+struct ApplyShape {
+    int nc, groups, nsplit, chunk;
+};
+
+static ApplyShape apply_shape(int64_t bk, int64_t ncols) {
+    ApplyShape a{};
+    a.nc = ncols >= 16 ? 16 : ncols >= 8 ? 8 : ncols >= 4 ? 4 : (ncols >= 2 ? 2 : 1);
+    a.groups = static_cast<int>((ncols + a.nc - 1) / a.nc);
+    const int64_t rowblocks = (bk + 511) / 512;
+    int64_t ns = (2048 + rowblocks * a.groups - 1) / (rowblocks * a.groups);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, bk / (8 * ncols)));
+    ns = std::max<int64_t>(ns, (bk + 4096 / a.nc - 1) / (4096 / a.nc));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, bk));
+    const int64_t chunk = (bk + ns - 1) / ns;
+    a.chunk = static_cast<int>(chunk);
+    a.nsplit = static_cast<int>((bk + chunk - 1) / chunk);
+    return a;
+}
 
 int64_t apply_workspace_doubles(const PlanData& P, int64_t ncols) {
     const int64_t bk = static_cast<int64_t>(P.b) * P.k;
-    return (2 + apply_nsplit(bk)) * bk * ncols + P.near_nnz * P.m_max * ncols;
+    return (2 + apply_shape(bk, ncols).nsplit) * bk * ncols;
 }
 
 void launch_ublr_apply(const PlanData& P, const DeviceTables& t, const double* U, const double* V,
                        const double* Atil, const double* Bv, int trans, int64_t ncols,
                        const double* x, int64_t ldx, double* y, int64_t ldy, double* work,
                        hipStream_t s) {
+    if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "k > 64 is not supported by the apply kernels");
+    if (ncols > INT32_MAX / 16) fail(BLR_ERR_INVALID_ARG, "too many vectors");
     const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+    const ApplyShape sh = apply_shape(bk, ncols);
     double* t1 = work;
     double* t2 = work + bk * ncols;
     double* part = work + 2 * bk * ncols;
     const double* Sin = trans ? U : V;
     const double* Sout = trans ? V : U;
-    hipLaunchKernelGGL(k_apply_proj, dim3(P.b, ncols), dim3(256), 0, s, Sin, P.n, t.box_ptr, P.k,
-                       x, ldx, t1, bk);
-    if (!trans) {
-        // Atil and B are read once per group of NC vectors
-        const int nsplit = apply_nsplit(bk);
-        const int chunk = static_cast<int>((bk + nsplit - 1) / nsplit);
-        double* npart = part + nsplit * bk * ncols;
-        const int nc = ncols >= 16 ? 16 : ncols >= 8 ? 8 : ncols >= 4 ? 4 : (ncols >= 2 ? 2 : 1);
-        const unsigned groups = static_cast<unsigned>((ncols + nc - 1) / nc);
-        auto run = [&](auto ncv) {
-            constexpr int NC = decltype(ncv)::value;
-            hipLaunchKernelGGL((k_gemv_nc<NC>), dim3((bk + 255) / 256, nsplit, groups), dim3(256), 0, s, Atil,
-                               bk, bk, t1, static_cast<int>(ncols), part, chunk);
-            hipLaunchKernelGGL(k_sum_parts, dim3((bk * ncols + 255) / 256), dim3(256), 0, s, part,
-                               nsplit, bk * ncols, t2);
-            hipLaunchKernelGGL((k_bsp_n<NC>), dim3(static_cast<unsigned>(P.near_nnz), groups), dim3(256), 0, s,
-                               t.box_ptr, t.near_idx, t.pair_row, t.b_off, Bv, P.m_max,
-                               P.near_nnz, x, ldx, static_cast<int>(ncols), npart);
-            hipLaunchKernelGGL((k_apply_out_n<NC>), dim3(P.b, groups), dim3(256), 0, s, Sout, P.n, t.box_ptr,
-                               P.k, t2, bk, t.near_ptr, P.m_max, P.near_nnz, npart, static_cast<int>(ncols), y, ldy);
-        };
-        if (nc == 16) run(std::integral_constant<int, 16>{});
-        else if (nc == 8) run(std::integral_constant<int, 8>{});
-        else if (nc == 4) run(std::integral_constant<int, 4>{});
-        else if (nc == 2) run(std::integral_constant<int, 2>{});
-        else run(std::integral_constant<int, 1>{});
-        check_launch("uBLR apply");
-        return;
-    } else {
+    const int nv = static_cast<int>(ncols);
+    const unsigned groups = static_cast<unsigned>(sh.groups);
+    auto run = [&](auto ncv) {
+        constexpr int NC = decltype(ncv)::value;
+        hipLaunchKernelGGL((k_proj_nc<NC>), dim3(P.b, groups), dim3(256), 0, s, Sin, P.n, t.box_ptr, P.k, x,
+                           ldx, nv, t1, bk);
+        if (!trans) {
+            hipLaunchKernelGGL((k_gemv_nc<NC>), dim3(static_cast<unsigned>((bk + 511) / 512), sh.nsplit, groups),
+                               dim3(256), static_cast<size_t>(sh.chunk) * NC * sizeof(double), s, Atil, bk, bk, t1,
+                               nv, part, sh.chunk);
+            hipLaunchKernelGGL(k_sum_parts, dim3((bk * ncols + 63) / 64), dim3(256), 0, s, part, sh.nsplit,
+                               bk * ncols, t2);
+            const dim3 grid(P.b, groups, static_cast<unsigned>((P.m_max + 63) / 64));
+            if constexpr (NC == 16)
+                hipLaunchKernelGGL((k_near_m16<0>), grid, dim3(256), 0, s, Sout, P.n, t.box_ptr, P.k, t2, bk,
+                                   t.near_ptr, t.near_idx, t.near_tpos, t.b_off, Bv, x, ldx, nv, y, ldy);
+            else
+                hipLaunchKernelGGL((k_near_out_n<NC>), grid, dim3(256), 0, s, Sout, P.n, t.box_ptr, P.k, t2, bk,
+                                   t.near_ptr, t.near_idx, t.b_off, Bv, x, ldx, nv, y, ldy);
+        }
+    };
+    if (sh.nc == 16) run(std::integral_constant<int, 16>{});
+    else if (sh.nc == 8) run(std::integral_constant<int, 8>{});
+    else if (sh.nc == 4) run(std::integral_constant<int, 4>{});
+    else if (sh.nc == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 1>{});
+    if (trans) {
+        // B_io^T is read across its columns: the MFMA form reads 16 of them per wave as whole
+        // cache lines, for any number of vectors
         hipLaunchKernelGGL(k_gemv_t, dim3((bk + 3) / 4, ncols), dim3(256), 0, s, Atil, bk, bk, t1, t2);
+        const unsigned g16 = static_cast<unsigned>((ncols + 15) / 16);
+        hipLaunchKernelGGL((k_near_m16<1>), dim3(P.b, g16, static_cast<unsigned>((P.m_max + 63) / 64)), dim3(256),
+                           0, s, Sout, P.n, t.box_ptr, P.k, t2, bk, t.near_ptr, t.near_idx, t.near_tpos, t.b_off, Bv,
+                           x, ldx, nv, y, ldy);
     }
-    hipLaunchKernelGGL(k_apply_out, dim3(P.b, ncols), dim3(256), 0, s, Sout, P.n, t.box_ptr, P.k,
-                       t2, bk, t.near_ptr, t.near_idx, t.near_tpos, t.b_off, Bv, trans, x, ldx, y, ldy);
     check_launch("uBLR apply");
 }
 
