@@ -345,7 +345,10 @@ typedef struct blr_report {
  * stacked Gaussian blocks G_i, H_i of Alg. 2 drawn by the caller.  opts may
  * be NULL (FP64, no intermediates).  On success *out owns device U, V
  * (N x k), Atil (bk x bk) and B (b_values doubles); it keeps a reference to
- * the plan.  If rep is non-NULL the call synchronises the stream and fills it.
+ * the plan.  If rep is non-NULL the call synchronises the stream, checks U,
+ * V, Atil and B for non-finite values (BLR_ERR_NUMERICAL, no handle returned:
+ * a non-finite sketch or basis shows up in them) and fills the report; without
+ * a report nothing waits and nothing is checked.
  */
 blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
                             const double* H, const blr_compress_opts* opts, void* stream,

@@ -678,10 +678,17 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         h->B = dalloc_sync(P.b_values);
         AsyncTemps tmp(s);
 
-        hipEvent_t ev[8];
         const bool timing = rep != nullptr;
+        struct Events {  // destroyed on every exit, errors included
+            hipEvent_t e[8] = {};
+            ~Events() {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } evs;
+        hipEvent_t* ev = evs.e;
         if (timing)
-            for (auto& e : ev) HIPC(hipEventCreate(&e));
+            for (int q = 0; q < 8; ++q) HIPC(hipEventCreate(&ev[q]));
         auto mark = [&](int q) {
             if (timing) HIPC(hipEventRecord(ev[q], s));
         };
@@ -767,12 +774,20 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         nearfield_any(o, P, t, h->U, h->V, h->Atil, h->B, s, tmp);
         mark(7);
         if (timing) {
+            // with a report the call waits for the device anyway: check U, V, Atil and B
+            double* flag = tmp.get(1);
+            const double* arrs[4] = {h->U, h->V, h->Atil, h->B};
+            const int64_t cnts[4] = {P.n * P.k, P.n * P.k, bk * bk, P.b_values};
+            launch_flag_nonfinite(arrs, cnts, 4, flag, s);
+            double hflag = 0.0;
+            HIPC(hipMemcpyAsync(&hflag, flag, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
+            if (hflag != 0.0)
+                fail(BLR_ERR_NUMERICAL, "non-finite values in the compressed operator (sketch, bases, cores or near field)");
             float ms[7];
             for (int q = 0; q < 7; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
             float tot;
             HIPC(hipEventElapsedTime(&tot, ev[0], ev[7]));
-            for (auto& e : ev) (void)hipEventDestroy(e);
             std::memset(rep, 0, sizeof(*rep));
             rep->ms_sketch = ms[0];
             rep->ms_postprocess = ms[1];

@@ -2116,6 +2116,33 @@ void launch_err_fro(const OpData& op, const PlanData& P, const DeviceTables& t, 
     check_launch("Frobenius error");
 }
 
+// flag[0] = 1 if any of the n values is not finite (flag[0] is set to 0 first by the
+// launcher's one-block fill; every writer stores the same value).
+__global__ __launch_bounds__(256) void k_zero1(double* __restrict__ flag) {
+    if (threadIdx.x == 0) flag[0] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_flag_nonfinite(const double* __restrict__ p, int64_t n,
+                                                        double* __restrict__ flag) {
+    bool bad = false;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; q < n;
+         q += static_cast<int64_t>(gridDim.x) * 256)
+        bad |= !isfinite(p[q]);
+    if (bad) flag[0] = 1.0;
+}
+
+void launch_flag_nonfinite(const double* const* arrays, const int64_t* counts, int narrays, double* flag,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(256), 0, s, flag);
+    for (int q = 0; q < narrays; ++q) {
+        if (counts[q] <= 0) continue;
+        const int64_t blocks = std::min<int64_t>(4096, (counts[q] + 255) / 256);
+        hipLaunchKernelGGL(k_flag_nonfinite, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, arrays[q],
+                           counts[q], flag);
+    }
+    check_launch("finiteness check");
+}
+
 int dot_parts() { return 1 + kDotBlocks; }
 
 void launch_dot(const double* x, const double* y, int64_t n, double* part, hipStream_t s) {

@@ -114,6 +114,9 @@ void launch_err_fro(const OpData& op, const PlanData& P, const DeviceTables& t, 
 // Deterministic dot product: part needs dot_parts() doubles; result in part[0].
 int dot_parts();
 void launch_dot(const double* x, const double* y, int64_t n, double* part, hipStream_t s);
+// flag[0] (device) = 1 if any value of the given device arrays is not finite, else 0
+void launch_flag_nonfinite(const double* const* arrays, const int64_t* counts, int narrays, double* flag,
+                           hipStream_t s);
 // y = a*x + y
 void launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 void launch_scale(double a, double* x, int64_t n, hipStream_t s);
