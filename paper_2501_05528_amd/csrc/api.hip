@@ -145,7 +145,9 @@ void require_entries(const OpData& o, const char* what) {
 void op_apply(const OpData& o, int trans, int64_t ncols, const double* X, int64_t ldx, double* Y,
               int64_t ldy, hipStream_t s) {
     if (!is_callback(o)) {
-        launch_op_apply(o, trans, ncols, X, ldx, Y, ldy, s);
+        const int64_t nw = op_apply_workspace_doubles(o, ncols);
+        AsyncTemps tmp(s);
+        launch_op_apply(o, trans, ncols, X, ldx, Y, ldy, nw > 0 ? tmp.get(nw) : nullptr, s);
         return;
     }
     const int32_t rc = o.fn(o.ctx, trans, ncols, X, ldx, Y, ldy, static_cast<void*>(s));

@@ -1879,11 +1879,99 @@ void launch_refine(const OpData& op, const PlanData& P, const DeviceTables& t, c
     }
 }
 
+// Products with at most four columns on kernel-matrix operators: the matrix cores would
+// idle on 16-column tiles, so each thread owns one target row and accumulates entry times
+// x on the vector ALU, the source range split over gridDim.y workgroups whose partial sums
+// a second kernel adds in split order.  Source contexts and x rows are staged in LDS in
+// chunks of 256 and read as broadcasts.
+template <class AS, int NC>
+__global__ __launch_bounds__(256) void k_opgemv(AS A, const double* __restrict__ X, int64_t ldx, int ncols,
+                                                int64_t M, int64_t K, int64_t chunk, double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    A.prepare((BLR_LDS double*)s_ltab);
+    constexpr int ST = AS::STAGE;
+    __shared__ double sc[256 * ST];
+    __shared__ double sx[256 * NC];
+    const int tid = threadIdx.x;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+    const bool rowok = i < M;
+    const auto rp = A.row(rowok ? i : M - 1);
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * chunk;
+    const int64_t k1 = min(K, k0 + chunk);
+    double acc[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+    for (int64_t c0 = k0; c0 < k1; c0 += 256) {
+        const int cl = static_cast<int>(min<int64_t>(256, k1 - c0));
+        __syncthreads();
+        if (tid < cl) {
+            A.stage(c0 + tid, &sc[tid * ST]);
+#pragma unroll
+            for (int v = 0; v < NC; ++v) sx[tid * NC + v] = v < ncols ? X[c0 + tid + static_cast<int64_t>(v) * ldx] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int u = 0; u < cl; ++u) {
+            const double a = A.val(rp, A.col_staged(&sc[u * ST], c0 + u));
+#pragma unroll
+            for (int v = 0; v < NC; ++v) acc[v] = fma(a, sx[u * NC + v], acc[v]);
+        }
+    }
+    if (rowok) {
+#pragma unroll
+        for (int v = 0; v < NC; ++v)
+            if (v < ncols) part[(static_cast<int64_t>(blockIdx.y) * ncols + v) * M + i] = acc[v];
+    }
+}
+
+template <class OUT>
+__global__ __launch_bounds__(256) void k_opgemv_sum(const double* __restrict__ part, int nsplit, int64_t M,
+                                                    int ncols, OUT O) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= M * ncols) return;
+    const int v = static_cast<int>(idx / M);
+    const int64_t i = idx - static_cast<int64_t>(v) * M;
+    double acc = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) acc += part[static_cast<int64_t>(sp) * ncols * M + idx];
+    O.put(i, v, acc);
+}
+
+// source-range splits of k_opgemv: about eight waves per SIMD at this N
+static int opgemv_nsplit(int64_t n) {
+    const int64_t rowblocks = (n + 255) / 256;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(32, (8 * 1024 / 4 + rowblocks - 1) / rowblocks)));
+}
+
+int64_t op_apply_workspace_doubles(const OpData& op, int64_t ncols) {
+    if (op.type != OpType::Kernel || ncols > 4) return 0;
+    return static_cast<int64_t>(opgemv_nsplit(op.n)) * ncols * op.n;
+}
+
 void launch_op_apply(const OpData& op, int trans, int64_t ncols, const double* X, int64_t ldx,
-                     double* Y, int64_t ldy, hipStream_t s) {
+                     double* Y, int64_t ldy, double* work, hipStream_t s) {
     if (ncols > (1 << 30)) fail(BLR_ERR_INVALID_ARG, "too many columns");
-    DenseB B{X, ldx};
     SplitOut O{Y, Y, ldy, static_cast<int>(ncols)};
+    if (op_apply_workspace_doubles(op, ncols) > 0 && ncols > 0) {
+        if (!work) fail(BLR_ERR_INVALID_ARG, "operator product: missing workspace");
+        const int ns = opgemv_nsplit(op.n);
+        const int64_t chunk = (op.n + ns - 1) / ns;
+        const dim3 grid(static_cast<unsigned>((op.n + 255) / 256), ns);
+        const int nc = static_cast<int>(ncols);
+        with_source(op, trans, [&](auto A) {
+            using AS = decltype(A);
+            if (nc == 1)
+                hipLaunchKernelGGL((k_opgemv<AS, 1>), grid, dim3(256), 0, s, A, X, ldx, nc, op.n, op.n, chunk, work);
+            else if (nc == 2)
+                hipLaunchKernelGGL((k_opgemv<AS, 2>), grid, dim3(256), 0, s, A, X, ldx, nc, op.n, op.n, chunk, work);
+            else
+                hipLaunchKernelGGL((k_opgemv<AS, 4>), grid, dim3(256), 0, s, A, X, ldx, nc, op.n, op.n, chunk, work);
+        });
+        hipLaunchKernelGGL(k_opgemv_sum<SplitOut>, dim3(static_cast<unsigned>((op.n * ncols + 255) / 256)), dim3(256),
+                           0, s, work, ns, op.n, nc, O);
+        check_launch("operator product (few columns)");
+        return;
+    }
+    DenseB B{X, ldx};
     with_source(op, trans, [&](auto A) { gemm_launch(A, B, O, op.n, op.n, static_cast<int>(ncols), s); });
 }
 

@@ -15,8 +15,11 @@ void launch_sketch(const OpData& op, const PlanData& P, const DeviceTables& t, c
                    const double* H, double* Y, double* Z, hipStream_t s);
 
 // Y = A X or A* X for a dense X (n x ncols).
+// Y = op(A) X for a built-in operator; work holds op_apply_workspace_doubles(op, ncols)
+// doubles (NULL when that is 0)
+int64_t op_apply_workspace_doubles(const OpData& op, int64_t ncols);
 void launch_op_apply(const OpData& op, int trans, int64_t ncols, const double* X, int64_t ldx,
-                     double* Y, int64_t ldy, hipStream_t s);
+                     double* Y, int64_t ldy, double* work, hipStream_t s);
 
 void launch_postprocess(const PlanData& P, const DeviceTables& t, const double* Y, double* Yhat,
                         hipStream_t s);

@@ -199,12 +199,13 @@ def test_apply_parity(run):
 def test_operator_apply_parity(run):
     P = run["P"]
     g = run["c"]["g"]
-    x = np.random.default_rng(4).standard_normal((g.n, 2))
-    xd = P.colmajor(x)
-    for trans in (False, True):
-        y = _np(run["op"].apply(xd, trans=trans))
-        ref = (run["A"].T if trans else run["A"]) @ x
-        _close(y, ref, 1e-12)
+    for ncols in (1, 2, 3, 4, 5):      # few-column VALU form up to 4 columns, MFMA tiles beyond
+        x = np.random.default_rng(4 + ncols).standard_normal((g.n, ncols))
+        xd = P.colmajor(x)
+        for trans in (False, True):
+            y = _np(run["op"].apply(xd, trans=trans))
+            ref = (run["A"].T if trans else run["A"]) @ x
+            _close(y, ref, 1e-12)
 
 
 def test_power_estimate_parity(run):
