@@ -74,7 +74,20 @@ typedef struct blr_geometry {
     int32_t dim;                /* d in {1, 2, 3} */
     int32_t nboxes;             /* b >= 2 */
     const int64_t* box_ptr;     /* host, b+1 entries, box_ptr[0] = 0, strictly increasing */
-    const int32_t* box_lattice; /* host, b*dim entries, box i at [i*dim, i*dim+dim) */
+    const int32_t* box_lattice; /* host, b*dim entries, box i at [i*dim, i*dim+dim); may be
+                                   NULL when near_ptr is given */
+    /* Optional neighbour lists N_i as host CSR (near_ptr: b+1 entries from 0; near_idx:
+     * near_ptr[b] box indices).  Each list strictly ascending, i in N_i, and the relation
+     * symmetric (j in N_i iff i in N_j); every far field F_i = [b] \ N_i non-empty.
+     * NULL: strong admissibility on the lattice, N_i = boxes at Chebyshev lattice
+     * distance <= 1 (Section 2.5), with probe colours sum_t (lat_t mod 3) 3^t.  With
+     * explicit lists the probe colours of Table 1 step (III) are assigned greedily in box
+     * order: box i takes the smallest colour not held by an earlier box that shares a
+     * neighbour with it, so the neighbours of every box carry distinct colours.
+     * Errors: BLR_ERR_INVALID_ARG (malformed lists), BLR_ERR_GEOMETRY (asymmetric lists,
+     * empty far field). */
+    const int32_t* near_ptr;
+    const int32_t* near_idx;
 } blr_geometry;
 
 /*

@@ -20,7 +20,7 @@ reconstruct     steps (II)-(III) of Table 1, the uBLR apply, error metrics
 refine          mixed-precision tagging with one FP64 refinement sketch (not in the paper)
 """
 from . import admissibility, operators, tagging, reconstruct, refine  # noqa: F401
-from .admissibility import near_lists, far_lists, colours, num_tag_columns  # noqa: F401
+from .admissibility import near_lists, far_lists, colours, greedy_colours, lists_and_colours, num_tag_columns  # noqa: F401
 from .operators import DenseOperator, KernelOperator, CountingOperator  # noqa: F401
 from .tagging import (extended_test_matrix, null_space, projected_tags, aspect_ratio,  # noqa: F401
                       optimise_tag_vector, tag_plan, tag_postprocess, col_topk, tag_bases)

@@ -39,6 +39,35 @@ def colours(lattice: np.ndarray) -> np.ndarray:
                     dtype=np.int64)
 
 
+def greedy_colours(near: list[list[int]]) -> np.ndarray:
+    """Probe colours for caller-given neighbour lists (reading of Section 6.1 for a general
+    neighbour relation): the probes need every box's neighbours to carry distinct colours,
+    i.e. two boxes that share a neighbour differ.  Boxes are taken in index order and each
+    gets the smallest colour not used by an earlier box within two neighbour steps."""
+    b = len(near)
+    colour = [-1] * b
+    for i in range(b):
+        taken = set()
+        for j in near[i]:
+            for l in near[j]:
+                if colour[l] >= 0:
+                    taken.add(colour[l])
+        c = 0
+        while c in taken:
+            c += 1
+        colour[i] = c
+    return np.array(colour, dtype=np.int64)
+
+
+def lists_and_colours(lattice, near=None):
+    """(near, colours): the lattice rule and its mod-3 colours, or the given lists with
+    greedy colours."""
+    if near is None:
+        return near_lists(lattice), colours(lattice)
+    near = [sorted(int(j) for j in n) for n in near]
+    return near, greedy_colours(near)
+
+
 def num_tag_columns(near: list[list[int]], extra: int = 3) -> int:
     """Columns of T: one more than the largest neighbour count (Section 4.1), plus
     ``extra`` columns that make every null space at least (extra+1)-dimensional

@@ -134,18 +134,18 @@ def power_norm_estimate(apply, apply_t, n: int, x0: np.ndarray, iters: int = 20)
 
 
 def reconstruct_tag(op, box_ptr, lattice, k: int, p: int, extra: int, T, G, H,
-                    optimise: bool = True, steps=("I", "II", "III")):
+                    optimise: bool = True, steps=("I", "II", "III"), near=None):
     """reconstruct_tag of Table 1: [U, V] = tag(A, A*, k); Atil = U*(A V); B by probes.
 
     ``T`` must have num_tag_columns(near, extra) columns and G, H must be N x (k+p).
-    Returns a dict with every intermediate.
+    ``near``: optional neighbour lists replacing the lattice rule (probe colours then
+    greedy).  Returns a dict with every intermediate.
     """
     box_ptr = np.asarray(box_ptr, dtype=np.int64)
     b = len(box_ptr) - 1
     r = k + p
-    near = admissibility.near_lists(lattice)
+    near, col = admissibility.lists_and_colours(lattice, near)
     far = admissibility.far_lists(near, b)
-    col = admissibility.colours(lattice)
     ell = admissibility.num_tag_columns(near, extra)
     assert T.shape == (b, ell), (T.shape, (b, ell))
     assert G.shape == (int(box_ptr[-1]), r) and H.shape == G.shape

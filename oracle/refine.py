@@ -86,7 +86,7 @@ def refine_bases(op, U0, V0, gamma_u, gamma_v, box_ptr, far, k: int):
 
 
 def reconstruct_tag_refined(op, box_ptr, lattice, k: int, p: int, extra: int, T, G, H,
-                            gamma_u, gamma_v, optimise: bool = True):
+                            gamma_u, gamma_v, optimise: bool = True, near=None):
     """The mixed-precision pipeline with every step in FP64: Alg. 2 sketches with
     r_lo = G.shape[1] columns per tag column, post-processing, sample bases, one
     refinement sketch, then Table 1 steps (II)-(III).  ``p`` is the oversampling of
@@ -94,9 +94,8 @@ def reconstruct_tag_refined(op, box_ptr, lattice, k: int, p: int, extra: int, T,
     box_ptr = np.asarray(box_ptr, dtype=np.int64)
     b = len(box_ptr) - 1
     r_lo = G.shape[1]
-    near = admissibility.near_lists(lattice)
+    near, col = admissibility.lists_and_colours(lattice, near)
     far = admissibility.far_lists(near, b)
-    col = admissibility.colours(lattice)
     ell = admissibility.num_tag_columns(near, extra)
     assert T.shape == (b, ell) and H.shape == G.shape
     assert gamma_u.shape == (b, r_lo, k + p) and gamma_v.shape == gamma_u.shape

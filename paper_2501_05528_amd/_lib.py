@@ -18,7 +18,8 @@ P_f64 = POINTER(c_double)
 
 
 class Geometry(ctypes.Structure):
-    _fields_ = [("dim", c_int32), ("nboxes", c_int32), ("box_ptr", P_i64), ("box_lattice", P_i32)]
+    _fields_ = [("dim", c_int32), ("nboxes", c_int32), ("box_ptr", P_i64), ("box_lattice", P_i32),
+                ("near_ptr", P_i32), ("near_idx", P_i32)]
 
 
 class TagParams(ctypes.Structure):

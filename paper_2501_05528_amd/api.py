@@ -75,16 +75,44 @@ def _stream(stream):
     return c_void_p(s.cuda_stream)
 
 
-def _geometry(box_ptr, lattice):
+def near_csr(near):
+    """(near_ptr, near_idx) int32 arrays from neighbour lists (a list of index lists, or a
+    (ptr, idx) pair)."""
+    if isinstance(near, tuple) and len(near) == 2 and not isinstance(near[0], (list, tuple)):
+        return np.ascontiguousarray(near[0], np.int32), np.ascontiguousarray(near[1], np.int32)
+    ptr = np.zeros(len(near) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(n) for n in near])
+    idx = np.ascontiguousarray(np.concatenate([np.asarray(n, np.int32) for n in near]), np.int32)
+    return ptr, idx
+
+
+def _geometry(box_ptr, lattice, near=None):
+    """blr_geometry for box_ptr and a lattice (b x d) and/or explicit neighbour lists."""
     bp = np.ascontiguousarray(box_ptr, dtype=np.int64)
-    lat = np.ascontiguousarray(lattice, dtype=np.int32)
-    g = _lib.Geometry(lat.shape[1], lat.shape[0], bp.ctypes.data_as(_lib.P_i64),
-                      lat.ctypes.data_as(_lib.P_i32))
-    return g, (bp, lat)
+    b = len(bp) - 1
+    keep = [bp]
+    if lattice is not None:
+        lat = np.ascontiguousarray(lattice, dtype=np.int32)
+        if lat.ndim != 2 or lat.shape[0] != b:
+            raise ValueError("lattice must be b x d")
+        dim, latp = lat.shape[1], lat.ctypes.data_as(_lib.P_i32)
+        keep.append(lat)
+    elif near is not None:
+        dim, latp = 1, ctypes.cast(None, _lib.P_i32)
+    else:
+        raise ValueError("need a lattice or explicit neighbour lists")
+    if near is not None:
+        nptr, nidx = near_csr(near)
+        keep += [nptr, nidx]
+        np_p, ni_p = nptr.ctypes.data_as(_lib.P_i32), nidx.ctypes.data_as(_lib.P_i32)
+    else:
+        np_p = ni_p = ctypes.cast(None, _lib.P_i32)
+    g = _lib.Geometry(dim, b, bp.ctypes.data_as(_lib.P_i64), latp, np_p, ni_p)
+    return g, keep
 
 
-def tag_columns(box_ptr, lattice, extra_tag_cols: int = 3) -> int:
-    g, keep = _geometry(box_ptr, lattice)
+def tag_columns(box_ptr, lattice, extra_tag_cols: int = 3, near=None) -> int:
+    g, keep = _geometry(box_ptr, lattice, near)
     ell = c_int32()
     check(lib().blr_tag_columns(byref(g), extra_tag_cols, byref(ell)))
     return ell.value
@@ -94,13 +122,13 @@ class Plan:
     """Host plan: lists, colours, tag vectors z and aspect ratios rho."""
 
     def __init__(self, box_ptr, lattice, k: int, T, p: int = 10, extra_tag_cols: int = 3,
-                 aspect_opt: bool = True):
-        g, keep = _geometry(box_ptr, lattice)
+                 aspect_opt: bool = True, near=None):
+        g, keep = _geometry(box_ptr, lattice, near)
         Tf = np.asfortranarray(T, dtype=np.float64)
         prm = _lib.TagParams(k, p, extra_tag_cols, 1 if aspect_opt else 0,
                              Tf.ctypes.data_as(_lib.P_f64))
         h = c_void_p()
-        ell = tag_columns(box_ptr, lattice, extra_tag_cols)
+        ell = tag_columns(box_ptr, lattice, extra_tag_cols, near)
         if Tf.shape != (g.nboxes, ell):
             raise ValueError(f"T must be {g.nboxes} x {ell}, got {Tf.shape}")
         check(lib().blr_tag_plan(byref(g), byref(prm), byref(h)))

@@ -58,6 +58,7 @@ struct PlanData {
     std::vector<int32_t> kstep_ptr, kstep_box;  // 32-row source steps per box
     std::vector<uint8_t> nearm;                 // b x b neighbour mask
     std::vector<int32_t> pair_row;              // row box of each neighbour pair
+    bool custom_near = false;                   // neighbour lists given by the caller
     std::vector<double> T;    // column-major b x ell (as supplied)
     std::vector<double> z;    // column-major b x ell
     std::vector<double> rho;  // [b]

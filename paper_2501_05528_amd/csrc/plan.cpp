@@ -45,6 +45,59 @@ void neighbour_csr(int dim, int b, const int32_t* lat, std::vector<int32_t>& ptr
     }
 }
 
+// Neighbour lists of a geometry: the caller's CSR (validated) or the lattice rule.
+void geometry_near(const blr_geometry* g, std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {
+    const int b = g->nboxes;
+    if (!g->near_ptr) {
+        if (!g->box_lattice) fail(BLR_ERR_INVALID_ARG, "need box_lattice or explicit neighbour lists");
+        neighbour_csr(g->dim, b, g->box_lattice, ptr, idx);
+        return;
+    }
+    if (!g->near_idx) fail(BLR_ERR_INVALID_ARG, "near_ptr given without near_idx");
+    if (g->near_ptr[0] != 0) fail(BLR_ERR_INVALID_ARG, "near_ptr[0] must be 0");
+    for (int i = 0; i < b; ++i)
+        if (g->near_ptr[i + 1] < g->near_ptr[i]) fail(BLR_ERR_INVALID_ARG, "near_ptr must be non-decreasing");
+    if (static_cast<int64_t>(g->near_ptr[b]) > static_cast<int64_t>(b) * b)
+        fail(BLR_ERR_INVALID_ARG, "more neighbour entries than box pairs");
+    ptr.assign(g->near_ptr, g->near_ptr + b + 1);
+    idx.assign(g->near_idx, g->near_idx + g->near_ptr[b]);
+    for (int i = 0; i < b; ++i) {
+        bool self = false;
+        for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+            if (idx[q] < 0 || idx[q] >= b) fail(BLR_ERR_INVALID_ARG, "neighbour index out of range");
+            if (q > ptr[i] && idx[q] <= idx[q - 1]) fail(BLR_ERR_INVALID_ARG, "neighbour lists must be strictly ascending");
+            self |= idx[q] == i;
+        }
+        if (!self) fail(BLR_ERR_INVALID_ARG, "every box must be its own neighbour");
+    }
+}
+
+// Greedy distance-2 colouring for explicit lists: box i (in index order) takes the smallest
+// colour not held by an earlier box l with a common neighbour (l in N_j for some j in N_i).
+int greedy_colours(int b, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx,
+                   std::vector<int32_t>& colour) {
+    colour.assign(b, -1);
+    std::vector<int> seen;      // seen[c] == i + 1: colour c is taken for box i
+    int ncol = 0;
+    for (int i = 0; i < b; ++i) {
+        for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+            const int j = idx[q];
+            for (int u = ptr[j]; u < ptr[j + 1]; ++u) {
+                const int c = colour[idx[u]];
+                if (c >= 0) {
+                    if (c >= static_cast<int>(seen.size())) seen.resize(c + 1, 0);
+                    seen[c] = i + 1;
+                }
+            }
+        }
+        int c = 0;
+        while (c < static_cast<int>(seen.size()) && seen[c] == i + 1) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
 // ---------------------------------------------------------------- null space
 // Orthonormal basis (ell x s, column-major) of null(M) for M = T(N_i,:)
 // (n x ell), from the Householder QR of M^T.  Returns false if M^T is
@@ -349,11 +402,11 @@ bool box_tag(PlanData& P, int i, std::vector<double>& zout, double& rho) {
 }  // namespace
 
 int tag_columns(const blr_geometry* g, int extra) {
-    if (!g || g->dim < 1 || g->dim > 3 || g->nboxes < 2 || !g->box_lattice)
+    if (!g || g->dim < 1 || g->dim > 3 || g->nboxes < 2 || (!g->box_lattice && !g->near_ptr))
         fail(BLR_ERR_INVALID_ARG, "tag_columns: bad geometry");
     if (extra < 0) fail(BLR_ERR_INVALID_ARG, "extra_tag_cols must be >= 0");
     std::vector<int32_t> ptr, idx;
-    neighbour_csr(g->dim, g->nboxes, g->box_lattice, ptr, idx);
+    geometry_near(g, ptr, idx);
     int mx = 0;
     for (int i = 0; i < g->nboxes; ++i) mx = std::max(mx, ptr[i + 1] - ptr[i]);
     return mx + 1 + extra;
@@ -363,7 +416,8 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
     if (!g || !prm) fail(BLR_ERR_INVALID_ARG, "NULL geometry or params");
     if (g->dim < 1 || g->dim > 3) fail(BLR_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
     if (g->nboxes < 2) fail(BLR_ERR_INVALID_ARG, "need at least 2 boxes");
-    if (!g->box_ptr || !g->box_lattice) fail(BLR_ERR_INVALID_ARG, "NULL box_ptr or box_lattice");
+    if (!g->box_ptr) fail(BLR_ERR_INVALID_ARG, "NULL box_ptr");
+    if (!g->box_lattice && !g->near_ptr) fail(BLR_ERR_INVALID_ARG, "need box_lattice or explicit neighbour lists");
     if (prm->k < 1 || prm->p < 0 || prm->extra_tag_cols < 0)
         fail(BLR_ERR_INVALID_ARG, "need k >= 1, p >= 0, extra_tag_cols >= 0");
     if (!prm->T) fail(BLR_ERR_INVALID_ARG, "NULL tagging matrix T");
@@ -393,14 +447,15 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
         os << "k + p = " << P->r << " exceeds the smallest box (" << P->m_min << " points)";
         fail(BLR_ERR_INVALID_ARG, os.str());
     }
-    P->lattice.assign(g->box_lattice, g->box_lattice + static_cast<size_t>(b) * dim);
-    {
+    P->custom_near = g->near_ptr != nullptr;
+    if (g->box_lattice) {
+        P->lattice.assign(g->box_lattice, g->box_lattice + static_cast<size_t>(b) * dim);
         std::set<std::vector<int32_t>> uniq;
         for (int i = 0; i < b; ++i)
             if (!uniq.insert(std::vector<int32_t>(&P->lattice[i * dim], &P->lattice[i * dim] + dim)).second)
                 fail(BLR_ERR_INVALID_ARG, "duplicate box lattice coordinates");
     }
-    neighbour_csr(dim, b, P->lattice.data(), P->near_ptr, P->near_idx);
+    geometry_near(g, P->near_ptr, P->near_idx);
     P->near_nnz = static_cast<int64_t>(P->near_idx.size());
     int maxnear = 0;
     for (int i = 0; i < b; ++i) {
@@ -414,18 +469,22 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
     }
     P->ell = maxnear + 1 + P->extra;
     // colours
-    P->ncol = 1;
-    for (int t = 0; t < dim; ++t) P->ncol *= 3;
-    P->colour.resize(b);
-    for (int i = 0; i < b; ++i) {
-        int c = 0, w = 1;
-        for (int t = 0; t < dim; ++t) {
-            int v = P->lattice[i * dim + t] % 3;
-            if (v < 0) v += 3;
-            c += v * w;
-            w *= 3;
+    if (P->custom_near) {
+        P->ncol = greedy_colours(b, P->near_ptr, P->near_idx, P->colour);
+    } else {
+        P->ncol = 1;
+        for (int t = 0; t < dim; ++t) P->ncol *= 3;
+        P->colour.resize(b);
+        for (int i = 0; i < b; ++i) {
+            int c = 0, w = 1;
+            for (int t = 0; t < dim; ++t) {
+                int v = P->lattice[i * dim + t] % 3;
+                if (v < 0) v += 3;
+                c += v * w;
+                w *= 3;
+            }
+            P->colour[i] = c;
         }
-        P->colour[i] = c;
     }
     P->colour_ptr.assign(P->ncol + 1, 0);
     for (int i = 0; i < b; ++i) P->colour_ptr[P->colour[i] + 1]++;

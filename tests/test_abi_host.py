@@ -133,3 +133,62 @@ def test_null_outputs_are_rejected():
     assert L.blr_tag_columns(ctypes.byref(geo), 3, None) == 1
     assert L.blr_tag_plan(ctypes.byref(geo), None, None) == 1
     assert b"NULL" in L.blr_last_error_message()
+
+
+def chebyshev_lists(lattice, radius):
+    """Neighbour lists for a wider admissibility: lattice Chebyshev distance <= radius."""
+    lat = np.asarray(lattice)
+    return [[j for j in range(len(lat)) if int(np.max(np.abs(lat[i] - lat[j]))) <= radius]
+            for i in range(len(lat))]
+
+
+@pytest.mark.parametrize("dim,B,radius", [(2, 7, 2), (1, 12, 1), (3, 5, 1), (2, 6, 1)])
+def test_plan_with_explicit_lists_matches_oracle(dim, B, radius):
+    from paper_2501_05528_amd.api import Plan, tag_columns
+    g = W.grid_geometry(dim, B, 3)
+    near = chebyshev_lists(g.lattice, radius)
+    far = O.far_lists(near, g.nboxes)
+    ell = O.num_tag_columns(near, 3)
+    assert tag_columns(g.box_ptr, None, 3, near=near) == ell
+    T = W.tag_matrix(300 + dim, g.nboxes, ell)
+    pl = Plan(g.box_ptr, None, 2, T, p=1, extra_tag_cols=3, near=near)
+    near_ptr, near_idx, colour, _ = pl.lists()
+    assert near_idx.tolist() == [j for n in near for j in n]
+    assert colour.tolist() == O.greedy_colours(near).tolist()
+    assert pl.info["ncolours"] == int(np.max(colour)) + 1
+    for i in range(g.nboxes):           # every probe meets at most one neighbour per colour
+        assert len({int(colour[j]) for j in near[i]}) == len(near[i])
+    z, rho = pl.tags()
+    zo, rhoo = O.tag_plan(T, near, far)
+    assert np.allclose(rho, rhoo, rtol=1e-9, atol=0)
+    assert np.allclose(z, zo, rtol=0, atol=1e-9)
+    # the lattice together with the same lists: identical plan
+    pl2 = Plan(g.box_ptr, g.lattice, 2, T, p=1, extra_tag_cols=3, near=near)
+    assert all(np.array_equal(a, b) for a, b in zip(pl.lists(), pl2.lists()))
+
+
+def test_explicit_list_errors():
+    from paper_2501_05528_amd.api import BlrError, Plan
+    g = W.grid_geometry(2, 5, 3)
+    near = chebyshev_lists(g.lattice, 1)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(7, g.nboxes, ell)
+    cases = []
+    no_self = [list(n) for n in near]
+    no_self[3].remove(3)
+    cases.append((no_self, "BLR_ERR_INVALID_ARG", T))
+    unsorted = [list(n) for n in near]
+    unsorted[4] = unsorted[4][::-1]
+    cases.append((unsorted, "BLR_ERR_INVALID_ARG", T))
+    out_of_range = [list(n) for n in near]
+    out_of_range[0] = out_of_range[0] + [g.nboxes]
+    cases.append((out_of_range, "BLR_ERR_INVALID_ARG", T))
+    asym = [list(n) for n in near]
+    asym[0] = sorted(asym[0] + [24])     # 24 lists no 0
+    cases.append((asym, "BLR_ERR_GEOMETRY", W.tag_matrix(7, g.nboxes, O.num_tag_columns(asym, 3))))
+    everything = [list(range(g.nboxes)) for _ in range(g.nboxes)]
+    cases.append((everything, "BLR_ERR_GEOMETRY", W.tag_matrix(7, g.nboxes, g.nboxes + 4)))
+    for lists, name, Tc in cases:
+        with pytest.raises(BlrError) as e:
+            Plan(g.box_ptr, None, 2, Tc, p=1, extra_tag_cols=3, near=lists)
+        assert e.value.name == name, (name, e.value)

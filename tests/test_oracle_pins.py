@@ -525,3 +525,45 @@ def test_p11_each_side_uses_the_other_sides_basis():
         s = np.linalg.svd(F, compute_uv=False)
         Ui = U[ri]
         assert np.linalg.norm(F - Ui @ (Ui.T @ F), 2) <= 10 * s[k], i
+
+
+def test_greedy_colours_chain_and_validity():
+    """Greedy probe colours for given lists: on a 1D chain they are i mod 3 (the lattice
+    colouring, which puts boxes 1, 4, 7 in one class as in the paper's probe figure), and
+    for any symmetric relation no box has two neighbours of one colour."""
+    b = 10
+    chain = [[j for j in (i - 1, i, i + 1) if 0 <= j < b] for i in range(b)]
+    assert O.greedy_colours(chain).tolist() == [i % 3 for i in range(b)]
+    assert O.greedy_colours(chain).tolist() == O.colours(np.arange(b)[:, None]).tolist()
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        n = 15
+        M = rng.random((n, n)) < 0.2
+        M = M | M.T | np.eye(n, dtype=bool)
+        near = [list(np.flatnonzero(M[i])) for i in range(n)]
+        col = O.greedy_colours(near)
+        for i in range(n):
+            assert len({int(col[j]) for j in near[i]}) == len(near[i])
+        # greedy bound: at most one more colour than the largest two-step neighbourhood
+        two = max(len({l for j in near[i] for l in near[j]}) for i in range(n))
+        assert int(col.max()) + 1 <= two
+
+
+def test_planted_exact_recovery_with_wider_admissibility():
+    """A planted uniform-BLR matrix whose blocks are low rank beyond lattice distance 1 is
+    still exactly recovered when distance <= 2 is declared near: the far field only shrinks
+    (Section 2.5 with a caller-given neighbour relation)."""
+    g = W.grid_geometry(2, 6, 4)
+    k, p = 3, 5
+    A, _, _ = W.planted_exact_rank(g, k, 11)
+    lat = np.asarray(g.lattice)
+    near = [[j for j in range(g.nboxes) if int(np.max(np.abs(lat[i] - lat[j]))) <= 2]
+            for i in range(g.nboxes)]
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(11, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(11, g.n, k + p)
+    op = O.DenseOperator(A)
+    res = O.reconstruct_tag(op, g.box_ptr, None, k, p, 3, T, G, H, near=near)
+    assert res["ell"] == 29 and int(res["colour"].max()) + 1 >= 25
+    err = O.rel_fro_error(op, res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k)
+    assert err <= 1e-12, err
