@@ -273,16 +273,21 @@ def batch_section(njobs=24, seed=20250104, n_lo=4096, n_hi=32768):
 
 
 def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
-    """Poisson arrivals of a job mix (4 in 5 from the batch generator in the BF16 mixed
-    mode, 1 in 5 the 2D Laplace N = 65536, k = 32 job): a 4-slot server with HBM-budget
-    admission against plain FP64 one at a time (1 slot), same arrivals."""
+    """Poisson arrivals of a job mix in the BF16 mixed mode: jobs from the batch generator,
+    every fifth one the 2D Laplace N = 65536, k = 32 job and two the 2D Laplace N = 262144,
+    k = 48 job (32 x 32 boxes); a 4-slot server with HBM-budget admission against plain FP64
+    one at a time (1 slot), same arrivals."""
     import torch
     import paper_2501_05528_amd as P
     gen = W.uneven_batch_jobs(njobs, seed, n_lo=4096, n_hi=32768)
     lap = _job_inputs(P, torch, W.WORKLOADS["laplace2d_n65536"], "bf16")
+    big = _job_inputs(P, torch, W.WORKLOADS["laplace2d_n262144"], "bf16")
     mix = []
     for q, wl in enumerate(gen):
-        mix.append(lap if q % 5 == 4 else _job_inputs(P, torch, wl, "bf16"))
+        if q % 24 == 11:
+            mix.append(big)
+        else:
+            mix.append(lap if q % 5 == 4 else _job_inputs(P, torch, wl, "bf16"))
     torch.cuda.synchronize()
     rng = W.rng(seed, W.STREAM_ARRIVALS)
 
@@ -307,7 +312,11 @@ def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
                 "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2)}
 
-    out = {"jobs": len(mix), "slots": 4, "admission": "FIFO by HBM footprint (160 GiB budget)"}
+    nbig = sum(1 for j in mix if j is big)
+    nlap = sum(1 for j in mix if j is lap)
+    out = {"jobs": len(mix), "mix": {"generator": len(mix) - nbig - nlap, "laplace2d_n65536": nlap,
+                                     "laplace2d_n262144": nbig},
+           "slots": 4, "admission": "FIFO by HBM footprint (160 GiB budget)"}
     for rate in rates:
         gaps = rng.exponential(1.0 / rate, size=len(mix))   # the same arrivals for both
         out[f"rate_{int(rate)}"] = {"served_bf16": drive(gaps, "bf16", 4),
