@@ -400,8 +400,11 @@ blr_status blr_ublr_export(const blr_ublr* h, int32_t part, void* host, int64_t 
 /*
  * y = A_uBLR x = U (Atil (V* x)) + B x (trans = 0) or A_uBLR* x (trans = 1)
  * (eq. uniformBLRfull), x: N x ncols device (ldx >= N), y: N x ncols device
- * (ldy >= N).  Uses library-owned workspace in the handle, so calls on one
- * handle must not overlap in time on different streams.
+ * (ldy >= N), 1 <= ncols <= 65535 (0 does nothing).  The workspace
+ * ((2 + s) b k ncols doubles, s the column split of the Atil product) is allocated
+ * stream-ordered on `stream` for the call, so calls on one handle may run on
+ * different streams at the same time.  Vectors go in groups of up to 16 that
+ * read Atil and B once per group.
  */
 blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x, int64_t ldx,
                      double* y, int64_t ldy, void* stream);
