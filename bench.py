@@ -7,8 +7,8 @@ inputs (points, T, G, H) are resident in HBM before timing starts.  The
 default workload is the 2D Laplace kernel log|x - y| on a 256 x 256 grid
 (N = 65536), 16 x 16 boxes of 256 points, k = 32, p = 10, ell = 13, FP64.
 
-Prints one JSON line with the driver's fields plus the roofline of the
-dominant kernel (the sketch, FP64 MFMA) and a CPU baseline (the FP64 oracle
+Prints one JSON line (metric, value, unit, steps, timing, dtype, config) plus the
+roofline of the dominant kernel (the sketch, FP64 MFMA) and a CPU baseline (the FP64 oracle
 timed on a bounded sample of the same workload).
 """
 from __future__ import annotations
@@ -342,7 +342,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "multi-GPU sharding is not part of this build"}))
+                                   "sharding over several GPUs is not implemented"}))
         sys.exit(2)
     import torch
     log(f"setup {args.workload}")
