@@ -54,6 +54,9 @@ def _case(name):
     if name == "log_boxes306":          # boxes of more than 256 points
         g = W.grid_geometry(2, 4, (18, 17), jitter=0.2, seed=11)
         return dict(name=name, g=g, k=16, p=10, kind="log", seed=20250106)
+    if name == "line1d_k13":            # d = 1 (3 neighbours, ell = 7), odd rank
+        g = W.grid_geometry(1, 24, 90, jitter=0.2, seed=13)
+        return dict(name=name, g=g, k=13, p=10, kind="exp", seed=20250107)
     if name == "cos_uneven":
         g = W.irregular_grid_geometry([[9, 12, 10, 14, 11, 9], [10, 13, 9, 12, 11]], jitter=0.2, seed=9)
         return dict(name=name, g=g, k=20, p=10, kind="cos", seed=20250105)
@@ -61,7 +64,7 @@ def _case(name):
 
 
 CASES = ["planted", "laplace_n9216", "laplace_ragged_jitter", "invr3d_n8000", "exp_n2500", "cos_uneven",
-         "log_boxes306"]
+         "log_boxes306", "line1d_k13"]
 
 
 def _oracle(c):
