@@ -2006,7 +2006,10 @@ void launch_orth_cols(const PlanData& P, const DeviceTables& t, int r, int k, in
     const size_t big = static_cast<size_t>(P.m_max) * r * sizeof(double);
     const size_t lds_limit = 160 * 1024 - 4096;  // gfx950: 160 KiB per workgroup, minus statics
     if (small > lds_limit) fail(BLR_ERR_UNSUPPORTED, "k + p too large for the basis kernel");
-    const int m_in_lds = (small + big <= lds_limit) ? 1 : 0;
+    // The m x r block goes to LDS only while several workgroups still fit on a CU: with one
+    // workgroup per CU (256 x 42 doubles) the barriers of the column loop are exposed, and
+    // reading the block through the caches measured 30% faster.
+    const int m_in_lds = (small + big <= 40 * 1024) ? 1 : 0;
     const size_t dyn = small + (m_in_lds ? big : 0);
     if (dyn > 64 * 1024) {
         // raise the kernel's dynamic LDS limit once per device and size (not during a
