@@ -934,7 +934,28 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
         }
         __syncthreads();
         const double vv = vvs[j];
-        for (int c = j + 1 + wave; c < r; c += 4) {
+        // two columns per wave at a time: their reductions and updates are independent
+        int c = j + 1 + wave;
+        for (; c + 4 < r; c += 8) {
+            double* y = M + static_cast<int64_t>(c) * ldm;
+            double* y2 = M + static_cast<int64_t>(c + 4) * ldm;
+            double d = 0.0, d2 = 0.0;
+            for (int a = j + lane; a < m; a += 64) {
+                const double xa = x[a];
+                d = fma(xa, y[a], d);
+                d2 = fma(xa, y2[a], d2);
+            }
+            d = wave_sum(d);
+            d2 = wave_sum(d2);
+            const double f = vv > 0.0 ? 2.0 * d / vv : 0.0;
+            const double f2 = vv > 0.0 ? 2.0 * d2 / vv : 0.0;
+            for (int a = j + lane; a < m; a += 64) {
+                const double xa = x[a];
+                y[a] -= f * xa;
+                y2[a] -= f2 * xa;
+            }
+        }
+        if (c < r) {
             double* y = M + static_cast<int64_t>(c) * ldm;
             double d = 0.0;
             for (int a = j + lane; a < m; a += 64) d += x[a] * y[a];
@@ -956,16 +977,17 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     __syncthreads();
     // 2. one-sided Jacobi on the columns of Rt, rotations accumulated in J
     // (skipped in QR-only mode: then U = the first k columns of Q).  Each round's
-    // nr/2 column pairs (round-robin order) are disjoint; a group of 16 lanes
+    // nr/2 column pairs (round-robin order) are disjoint; a group of 8 lanes
     // rotates one pair, its lanes striding over the r entries and reducing the
-    // three inner products with in-group shuffles; 16 groups share a round.
+    // three inner products with in-group shuffles; 32 groups share a round, so
+    // up to 64 columns take one pass per round.
     const double tol = sqrt(static_cast<double>(r)) * 2.220446049250313e-16;
     const int nr = r + (r & 1);
-    const int grp = tid >> 4, gl = tid & 15;
+    const int grp = tid >> 3, gl = tid & 7;
     for (int sweep = 0; sweep < (qr_only ? 0 : max_sweeps); ++sweep) {
         int rotated = 0;
         for (int round = 0; round < nr - 1; ++round) {
-            for (int u = grp; u < nr / 2; u += 16) {
+            for (int u = grp; u < nr / 2; u += 32) {
                 int p = rr_player(u, round, nr), q = rr_player(nr - 1 - u, round, nr);
                 if (p > q) {
                     const int t = p;
@@ -976,17 +998,17 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
                 double* xp = Rt + p * r;
                 double* xq = Rt + q * r;
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int a = gl; a < r; a += 16) {
+                for (int a = gl; a < r; a += 8) {
                     const double x = xp[a], y = xq[a];
                     al = fma(x, x, al);
                     be = fma(y, y, be);
                     ga = fma(x, y, ga);
                 }
 #pragma unroll
-                for (int o = 8; o >= 1; o >>= 1) {
-                    al += __shfl_xor(al, o, 16);
-                    be += __shfl_xor(be, o, 16);
-                    ga += __shfl_xor(ga, o, 16);
+                for (int o = 4; o >= 1; o >>= 1) {
+                    al += __shfl_xor(al, o, 8);
+                    be += __shfl_xor(be, o, 8);
+                    ga += __shfl_xor(ga, o, 8);
                 }
                 if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
@@ -994,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
                     const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
                     double* jp = J + p * r;
                     double* jq = J + q * r;
-                    for (int a = gl; a < r; a += 16) {
+                    for (int a = gl; a < r; a += 8) {
                         const double x = xp[a], y = xq[a];
                         xp[a] = c * x - sn * y;
                         xq[a] = sn * x + c * y;
