@@ -917,25 +917,50 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
         ldm = ldS;
     }
     __syncthreads();
-    // 1. Householder QR
+    // 1. Householder QR.  Wave 0 forms reflector 0; afterwards the reflector of column j + 1
+    // is formed by wave 0 right after it applies reflector j to that column (look-ahead), with
+    // the same row-to-lane map as the update, so every column costs one barrier.
+    auto reflector = [&](int j, double s2, double x0) {   // wave 0, after the wave sums
+        const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
+        if (lane == 0) {
+            rdiag[j] = alpha;
+            vvs[j] = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+        }
+        return x0 - alpha;
+    };
+    if (wave == 0) {
+        double s2 = 0.0;
+        for (int a = lane; a < m; a += 64) s2 += M[a] * M[a];
+        s2 = wave_sum(s2);
+        const double x0 = M[0];
+        const double h = reflector(0, s2, x0);
+        if (lane == 0) M[0] = h;
+    }
+    __syncthreads();
     for (int j = 0; j < r; ++j) {
         double* x = M + static_cast<int64_t>(j) * ldm;
-        if (wave == 0) {
-            double s2 = 0.0;
-            for (int a = j + lane; a < m; a += 64) s2 += x[a] * x[a];
-            s2 = wave_sum(s2);
-            const double x0 = x[j];
-            const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
-            if (lane == 0) {
-                rdiag[j] = alpha;
-                vvs[j] = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-                x[j] = x0 - alpha;
-            }
-        }
-        __syncthreads();
         const double vv = vvs[j];
-        // two columns per wave at a time: their reductions and updates are independent
         int c = j + 1 + wave;
+        if (wave == 0 && j + 1 < r) {
+            double* y = M + static_cast<int64_t>(j + 1) * ldm;
+            double d = 0.0;
+            for (int a = j + lane; a < m; a += 64) d = fma(x[a], y[a], d);
+            d = wave_sum(d);
+            const double f = vv > 0.0 ? 2.0 * d / vv : 0.0;
+            double s2 = 0.0, y1 = 0.0;
+            for (int a = j + lane; a < m; a += 64) {
+                const double yn = y[a] - f * x[a];
+                y[a] = yn;
+                if (a > j) s2 = fma(yn, yn, s2);
+                if (a == j + 1) y1 = yn;
+            }
+            s2 = wave_sum(s2);
+            const double x0 = wave_sum(y1);                 // row j + 1 lives on lane 1 only
+            const double h = reflector(j + 1, s2, x0);
+            if (lane == 1) y[j + 1] = h;
+            c += 4;
+        }
+        // two columns per wave at a time: their reductions and updates are independent
         for (; c + 4 < r; c += 8) {
             double* y = M + static_cast<int64_t>(c) * ldm;
             double* y2 = M + static_cast<int64_t>(c + 4) * ldm;
@@ -1047,7 +1072,87 @@ __global__ __launch_bounds__(256) void k_orth(double* S0, double* S1, int64_t ld
     }
     __syncthreads();
     if (sigma && tid < r) sigma[static_cast<int64_t>(box) * r + tid] = norms[order[tid]];
-    // 4. U = Q [W_k; 0], applying H_{r-1} ... H_0; then the sign rule
+    // 4. U = Q [W_k; 0], applying H_{r-1} ... H_0; then the sign rule.  Boxes of at most 256
+    // rows keep four output columns of a wave in registers (lane l holds rows l + 64 t), so
+    // each reflector is read once for the four and their reductions overlap.
+    if (m <= 256) {
+        constexpr int MT = 4, CB = 4;
+        const int ncw = (k - wave + 3) / 4;          // this wave's columns t = wave + 4 q
+        for (int q0 = 0; q0 < ncw; q0 += CB) {
+            double u[CB][MT];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const bool valid = q0 + cb < ncw;
+                const double* w = J + order[valid ? wave + 4 * (q0 + cb) : wave] * r;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int a = lane + 64 * mt;
+                    u[cb][mt] = (valid && a < r) ? w[a] : 0.0;
+                }
+            }
+            for (int j = r - 1; j >= 0; --j) {
+                const double* x = M + static_cast<int64_t>(j) * ldm;
+                double xv[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int a = lane + 64 * mt;
+                    xv[mt] = (a >= j && a < m) ? x[a] : 0.0;
+                }
+                const double vv = vvs[j];
+                double d[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    d[cb] = 0.0;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) d[cb] = fma(xv[mt], u[cb][mt], d[cb]);
+                }
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) d[cb] = wave_sum(d[cb]);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const double f = vv > 0.0 ? 2.0 * d[cb] / vv : 0.0;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) u[cb][mt] -= f * xv[mt];
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (q0 + cb >= ncw) continue;
+                const int t = wave + 4 * (q0 + cb);
+                double best = -1.0, sval = 0.0;
+                int bi = 0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int a = lane + 64 * mt;
+                    const double v = fabs(u[cb][mt]);
+                    if (a < m && v > best) {
+                        best = v;
+                        bi = a;
+                        sval = u[cb][mt];
+                    }
+                }
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    const double ob = __shfl_xor(best, o, 64);
+                    const int oi = __shfl_xor(bi, o, 64);
+                    const double os = __shfl_xor(sval, o, 64);
+                    if (ob > best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                        sval = os;
+                    }
+                }
+                const double sg = sval < 0.0 ? -1.0 : 1.0;
+                double* uo = Q + r0 + static_cast<int64_t>(t) * ldQ;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int a = lane + 64 * mt;
+                    if (a < m) uo[a] = sg * u[cb][mt];
+                }
+            }
+        }
+        return;
+    }
     for (int t = wave; t < k; t += 4) {
         double* u = Q + r0 + static_cast<int64_t>(t) * ldQ;
         const double* w = J + order[t] * r;
