@@ -1548,6 +1548,76 @@ __global__ __launch_bounds__(256) void k_nf_b(
     }
 }
 
+// The same Q products on FP64 MFMA, for boxes of at most 16 RTW rows: the workgroup stages the
+// k x k block Atil(i, l') of each box l' of the colour in LDS (B operand, transposed) and
+// contracts it with V_l' read straight from HBM (A operand: 16 probe columns x 4 basis
+// columns per lane group); wave w owns the 16-row tiles w, w + 4, ... of Q and all its
+// KP / 16 column tiles, accumulated over the whole colour class.
+template <int RTW, int NTT>
+__global__ __launch_bounds__(256) void k_nf_q_m(const int64_t* __restrict__ box_ptr,
+                                                const int32_t* __restrict__ colour_ptr,
+                                                const int32_t* __restrict__ colour_boxes,
+                                                const int32_t* __restrict__ nf_pair, int ncol,
+                                                const double* __restrict__ V, int64_t ldUV,
+                                                const double* __restrict__ Atil, int64_t ldAt, int k,
+                                                int m_max, double* __restrict__ Qg) {
+    constexpr int KP = NTT * 16, SP = KP + 1;
+    __shared__ double sAt[KP * SP];  // sAt[s * SP + t] = Atil(i k + t, l' k + s), zero past k
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int pair = blockIdx.x;
+    const int i = pair / ncol, c = pair - (pair / ncol) * ncol;
+    if (nf_pair[pair] < 0) return;
+    const int cb0 = colour_ptr[c], cb1 = colour_ptr[c + 1];
+    const int nrt = (m_max + 15) / 16;
+    d4 acc[RTW][NTT];
+#pragma unroll
+    for (int rr = 0; rr < RTW; ++rr)
+#pragma unroll
+        for (int nt = 0; nt < NTT; ++nt) acc[rr][nt] = d4{0.0, 0.0, 0.0, 0.0};
+    const int srow = lane >> 4, lcol = lane & 15;
+#pragma unroll 1
+    for (int qq = cb0; qq < cb1; ++qq) {
+        const int lp = colour_boxes[qq];
+        const int64_t lp0 = box_ptr[lp];
+        const int mlp = static_cast<int>(box_ptr[lp + 1] - lp0);
+        __syncthreads();
+        for (int idx = tid; idx < KP * KP; idx += 256) {
+            const int t = idx % KP, sx = idx / KP;
+            sAt[sx * SP + t] = (t < k && sx < k)
+                ? Atil[(static_cast<int64_t>(i) * k + t) + (static_cast<int64_t>(lp) * k + sx) * ldAt] : 0.0;
+        }
+        __syncthreads();
+        for (int s0 = 0; s0 < k; s0 += 4) {
+            const int s2 = s0 + srow;                    // < KP: KP is a multiple of 16 >= k
+            double bb[NTT];
+#pragma unroll
+            for (int nt = 0; nt < NTT; ++nt) bb[nt] = sAt[s2 * SP + nt * 16 + lcol];
+#pragma unroll
+            for (int rr = 0; rr < RTW; ++rr) {
+                const int rt = wave + 4 * rr;
+                if (rt >= nrt) continue;                 // uniform over the wave
+                const int col = rt * 16 + lcol;
+                const double a = (col < mlp && s2 < k) ? V[lp0 + col + static_cast<int64_t>(s2) * ldUV] : 0.0;
+#pragma unroll
+                for (int nt = 0; nt < NTT; ++nt) acc[rr][nt] = mfma64(a, bb[nt], acc[rr][nt]);
+            }
+        }
+    }
+    double* Q = Qg + static_cast<int64_t>(pair) * m_max * KP;
+#pragma unroll
+    for (int rr = 0; rr < RTW; ++rr) {
+        const int rt = wave + 4 * rr;
+        if (rt >= nrt) continue;
+#pragma unroll
+        for (int nt = 0; nt < NTT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = rt * 16 + d_row(lane, v);
+                if (col < m_max) Q[static_cast<int64_t>(col) * KP + nt * 16 + d_col(lane)] = acc[rr][nt][v];
+            }
+    }
+}
+
 // out[idx] = sum_s part[s len + idx]: 64 outputs per workgroup; the four waves take every
 // fourth split and their sums meet in LDS.
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nsplit,
@@ -2198,6 +2268,31 @@ int64_t nearfield_workspace_doubles(const PlanData& P) {
     return static_cast<int64_t>(P.b) * P.ncol * P.m_max * kp;
 }
 
+// Q products of the near field: the MFMA form while a wave's accumulators stay within 16
+// tiles (boxes of at most 256 rows for k <= 64), else the VALU form.
+template <int KP>
+static void nf_q_launch(const PlanData& P, const DeviceTables& t, const double* V, const double* Atil,
+                        int64_t ldAt, double* work, hipStream_t s) {
+    constexpr int NTT = KP / 16;
+    const dim3 grid(P.b * P.ncol);
+    const int rtw = ((P.m_max + 15) / 16 + 3) / 4;
+#define BLR_NFQ_M(RTWV)                                                                                   \
+    hipLaunchKernelGGL((k_nf_q_m<RTWV, NTT>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes, \
+                       t.nf_pair, P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work)
+    if (rtw * NTT <= 16) {
+        switch (rtw) {
+            case 1: BLR_NFQ_M(1); return;
+            case 2: BLR_NFQ_M(2); return;
+            case 3: BLR_NFQ_M(3); return;
+            case 4: BLR_NFQ_M(4); return;
+            default: break;
+        }
+    }
+#undef BLR_NFQ_M
+    hipLaunchKernelGGL((k_nf_q<KP>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes, t.nf_pair,
+                       P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work);
+}
+
 void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t, const double* U,
                       const double* V, const double* Atil, double* Bv, double* work, hipStream_t s) {
     if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "k > 64 is not supported by the near-field kernel");
@@ -2206,8 +2301,7 @@ void launch_nearfield(const OpData& op, const PlanData& P, const DeviceTables& t
     const dim3 grid(P.b * P.ncol);
     auto run = [&](auto kpc) {
         constexpr int KP = decltype(kpc)::value;
-        hipLaunchKernelGGL((k_nf_q<KP>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes,
-                           t.nf_pair, P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work);
+        nf_q_launch<KP>(P, t, V, Atil, ldAt, work, s);
         with_source(op, 0, [&](auto A) {
             using AS = decltype(A);
             hipLaunchKernelGGL((k_nf_b<AS, KP>), grid, dim3(256), 0, s, A, t.box_ptr, t.near_idx, t.b_off,
@@ -2231,8 +2325,7 @@ void launch_nf_q(const PlanData& P, const DeviceTables& t, const double* V, cons
     const dim3 grid(P.b * P.ncol);
     auto run = [&](auto kpc) {
         constexpr int KP = decltype(kpc)::value;
-        hipLaunchKernelGGL((k_nf_q<KP>), grid, dim3(256), 0, s, t.box_ptr, t.colour_ptr, t.colour_boxes,
-                           t.nf_pair, P.ncol, V, P.n, Atil, ldAt, P.k, P.m_max, work);
+        nf_q_launch<KP>(P, t, V, Atil, ldAt, work, s);
     };
     switch (kp) {
         case 16: run(std::integral_constant<int, 16>{}); break;
