@@ -133,6 +133,7 @@ class Plan:
             raise ValueError(f"T must be {g.nboxes} x {ell}, got {Tf.shape}")
         check(lib().blr_tag_plan(byref(g), byref(prm), byref(h)))
         self._h = h
+        self._lib = lib()      # kept so that destruction at interpreter exit needs no module globals
         info = _lib.PlanInfo()
         check(lib().blr_plan_query(h, byref(info)))
         self.info = {f: getattr(info, f) for f, _ in _lib.PlanInfo._fields_}
@@ -160,8 +161,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().blr_plan_destroy(h)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.blr_plan_destroy(h)
             self._h = None
 
 
@@ -170,6 +171,7 @@ class Operator:
 
     def __init__(self, handle, n, keep=None):
         self._h = handle
+        self._lib = lib()      # kept so that destruction at interpreter exit needs no module globals
         self.n = n
         self._keep = keep
 
@@ -225,8 +227,8 @@ class Operator:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().blr_op_destroy(h)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.blr_op_destroy(h)
             self._h = None
 
 
@@ -235,6 +237,7 @@ class UBLR:
 
     def __init__(self, handle, plan: Plan, precision: str = "fp64", r_lo: int = 0, owner=None):
         self._h = handle
+        self._lib = lib()      # kept so that destruction at interpreter exit needs no module globals
         self.plan = plan
         self.precision = precision
         self.r_lo = r_lo or plan.r
@@ -288,8 +291,9 @@ class UBLR:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and getattr(self, "_owner", None) is None:
-            lib().blr_ublr_destroy(h)
+        owned = getattr(self, "_owner", None) is None
+        if h is not None and h.value and owned and getattr(self, "_lib", None) is not None:
+            self._lib.blr_ublr_destroy(h)
             self._h = None
 
 
@@ -326,6 +330,7 @@ class Batch:
         h = c_void_p()
         check(lib().blr_batch_create(len(jobs), arr, flags, byref(h)))
         self._h = h
+        self._lib = lib()      # kept so that destruction at interpreter exit needs no module globals
         self.njobs = len(jobs)
 
     def run(self, stream=None):
@@ -345,8 +350,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().blr_batch_destroy(h)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.blr_batch_destroy(h)
             self._h = None
 
 
@@ -358,6 +363,7 @@ class Server:
         h = c_void_p()
         check(lib().blr_server_create(int(hbm_budget), slots, byref(h)))
         self._h = h
+        self._lib = lib()      # kept so that destruction at interpreter exit needs no module globals
         self._pending = {}
 
     def submit(self, plan: Plan, op: Operator, G, H, precision: str = "fp64", gamma_u=None,
@@ -388,8 +394,8 @@ class Server:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().blr_server_destroy(h)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.blr_server_destroy(h)
             self._h = None
         self._pending = {}
 
