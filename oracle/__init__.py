@@ -18,8 +18,9 @@ operators       black-box operators: dense matrix and kernel matrices
 tagging         Alg. 2 (tagging) with the aspect-ratio optimisation of Section 5.3
 reconstruct     steps (II)-(III) of Table 1, the uBLR apply, error metrics
 refine          mixed-precision tagging with one FP64 refinement sketch (not in the paper)
+basic           Alg. 3 (basic randomized SVD per box), the paper's benchmark for step (I)
 """
-from . import admissibility, operators, tagging, reconstruct, refine  # noqa: F401
+from . import admissibility, operators, tagging, reconstruct, refine, basic  # noqa: F401
 from .admissibility import near_lists, far_lists, colours, greedy_colours, lists_and_colours, num_tag_columns  # noqa: F401
 from .operators import DenseOperator, KernelOperator, CountingOperator  # noqa: F401
 from .tagging import (extended_test_matrix, null_space, projected_tags, aspect_ratio,  # noqa: F401
@@ -28,3 +29,4 @@ from .reconstruct import (cores, nearfield_probes, ublr_apply, dense_reconstruct
                           rel_fro_error, power_norm_estimate, reconstruct_tag)
 from .refine import (sample_basis, sample_bases, mixed_test_blocks, far_sample,  # noqa: F401
                      refine_bases, reconstruct_tag_refined)
+from .basic import masked_test_matrix, basic_bases, reconstruct_basic  # noqa: F401
