@@ -147,6 +147,31 @@ def apply_section(S, h, reps=20):
     return out
 
 
+def basic_section(S, tag_value, with_error):
+    """One compression by Alg. 3 (b r masked test columns per side instead of ell r
+    tagged ones) on the same operator, plan, G and H: the paper's comparison of
+    products and time for step (I).  One untimed call first warms the code path."""
+    import torch
+    P, plan, op = S["P"], S["plan"], S["op"]
+    h, _ = P.basic_compress(plan, op, S["Gd"], S["Hd"], report=True)
+    del h
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h, rep = P.basic_compress(plan, op, S["Gd"], S["Hd"], report=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    err = h.error_fro(op) if with_error else None
+    log(f"basic: {1e3 * el:.1f} ms, samples {rep['ms_sketch']:.1f} ms, rel err {err}")
+    sk = rep["sketch_flops"] / (rep["ms_sketch"] * 1e-3) / 1e12
+    return {"value": round(1.0 / el, 4), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 3),
+            "tagging_speedup": round(tag_value * el, 3),
+            "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+            "rel_err_fro": err,
+            "stage_ms": {k: round(rep[k], 3) for k in ("ms_sketch", "ms_orth", "ms_cores",
+                                                       "ms_nearfield", "ms_total")},
+            "sample_TFLOPs": round(sk, 2), "sample_flops": rep["sketch_flops"]}
+
+
 def cpu_baseline(S, nsample_boxes=4):
     """The oracle, as it stands, on a bounded sample: every stage of reconstruct_tag
     restricted to `nsample_boxes` row boxes (sketch rows, their post-processing and
@@ -334,6 +359,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-job measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-basic", action="store_true",
+                    help="skip the one-off Alg. 3 (basic randomized SVD) comparison run")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (BF16 / FP32 sketch + FP64 refinement) runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -415,6 +442,12 @@ def main():
                                     "algorithmic_flops_per_launch": rp["refine_flops"]},
             }
         out["mixed"] = mixed
+    if not args.no_basic:
+        try:
+            log("Alg. 3 comparison (basic randomized SVD per box)")
+            out["basic_alg3"] = basic_section(S, value, not args.no_error)
+        except Exception as e:  # extra measurement: never lose the line
+            out["basic_alg3"] = {"error": repr(e)}
     if not args.no_batch:
         try:
             log("batched uneven jobs")

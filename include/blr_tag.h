@@ -366,6 +366,24 @@ typedef struct blr_report {
 blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const double* G,
                             const double* H, const blr_compress_opts* opts, void* stream,
                             blr_ublr** out, blr_report* rep);
+
+/*
+ * Alg. 3 (the paper's basic randomized SVD for step (I)) followed by steps
+ * (II)-(III) of Table 1: the comparison method that tagging replaces.  For
+ * every box i, A is applied to Omega^(i) = G with the rows of every box in
+ * N_i set to zero, and A* to Psi^(i) = H masked likewise; U_i and V_i are the
+ * top-k left singular vectors of the box's own rows of the two products (the
+ * same per-box basis routine as blr_tag_compress).  G and H (device, N x r
+ * column-major, ld N) are shared by all boxes: each box's sample sees an
+ * N(0,1) test matrix on its far field, which is all Alg. 3 uses.  Costs b r
+ * columns on each of A and A* (reported in applies_A / applies_At; ms_sketch
+ * covers all of them, ms_postprocess is 0).  keep_samples != 0 keeps the
+ * N x r per-box samples as BLR_PART_SY / BLR_PART_SZ.  Ownership, report and
+ * error behaviour as for blr_tag_compress (FP64 only, any operator).
+ */
+blr_status blr_basic_compress(const blr_plan* plan, const blr_operator* op, const double* G,
+                              const double* H, int32_t keep_samples, void* stream, blr_ublr** out,
+                              blr_report* rep);
 void blr_ublr_destroy(blr_ublr* h);
 
 /* Which device array of a compressed handle. */
@@ -382,7 +400,7 @@ typedef enum blr_ublr_part {
     BLR_PART_Z0 = 9,    /* float, N x ell r_lo                        (mixed, keep_intermediates) */
     BLR_PART_U0 = 10,   /* N x r_lo sample bases                      (mixed, keep_intermediates) */
     BLR_PART_V0 = 11,   /* N x r_lo                                   (mixed, keep_intermediates) */
-    BLR_PART_SY = 12,   /* N x r refinement samples                   (mixed, keep_intermediates) */
+    BLR_PART_SY = 12,   /* N x r refinement samples (mixed, keep_intermediates); per-box samples of blr_basic_compress */
     BLR_PART_SZ = 13    /* N x r                                      (mixed, keep_intermediates) */
 } blr_ublr_part;
 

@@ -428,6 +428,21 @@ def compress(plan: Plan, op: Operator, G, H, keep_intermediates: bool = False, r
     return out, rd
 
 
+def basic_compress(plan: Plan, op: Operator, G, H, keep_samples: bool = False, report: bool = True,
+                   stream=None):
+    """Alg. 3 (basic randomized SVD per box) for step (I), then steps (II)-(III) of
+    Table 1.  G and H: N x r column-major CUDA float64, masked per box inside the
+    library.  Returns (UBLR, report dict or None); keep_samples keeps parts "SY",
+    "SZ" (each box's own rows of its two products)."""
+    h = c_void_p()
+    rep = _lib.Report()
+    check(lib().blr_basic_compress(plan._h, op._h, _ptr(G), _ptr(H), 1 if keep_samples else 0,
+                                   _stream(stream), byref(h), byref(rep) if report else None))
+    out = UBLR(h, plan)
+    rd = {f: getattr(rep, f) for f, _ in _lib.Report._fields_} if report else None
+    return out, rd
+
+
 # ---------------------------------------------------------------- stages
 def sketch(plan: Plan, op: Operator, G, H, stream=None):
     LR = plan.ell * plan.r

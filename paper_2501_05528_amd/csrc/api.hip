@@ -817,6 +817,110 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
     });
 }
 
+blr_status blr_basic_compress(const blr_plan* plan, const blr_operator* op, const double* G,
+                              const double* H, int32_t keep_samples, void* stream, blr_ublr** out,
+                              blr_report* rep) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!G || !H) fail(BLR_ERR_INVALID_ARG, "NULL G or H");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = plan->d->tables();
+        const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+
+        auto h = std::make_unique<UblrData>();
+        h->plan = plan->d;
+        h->device = current_device();
+        h->precision = BLR_PREC_FP64;
+        h->U = dalloc_sync(P.n * P.k);
+        h->V = dalloc_sync(P.n * P.k);
+        h->Atil = dalloc_sync(bk * bk);
+        h->B = dalloc_sync(P.b_values);
+        AsyncTemps tmp(s);
+        // the basis routine overwrites its input: kept samples are copies
+        double* SY = tmp.get(P.n * P.r);
+        double* SZ = tmp.get(P.n * P.r);
+
+        const bool timing = rep != nullptr;
+        struct Events {
+            hipEvent_t e[5] = {};
+            ~Events() {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } evs;
+        hipEvent_t* ev = evs.e;
+        if (timing)
+            for (int q = 0; q < 5; ++q) HIPC(hipEventCreate(&ev[q]));
+        auto mark = [&](int q) {
+            if (timing) HIPC(hipEventRecord(ev[q], s));
+        };
+        // events: 0 start | 1 per-box samples | 2 bases | 3 cores | 4 near field
+        mark(0);
+        // Alg. 3: box i applies A (and A*) to G (H) with the rows of its neighbours
+        // zeroed and keeps its own rows of the product; boxes go in chunks so that
+        // one operator call sees many test matrices side by side.
+        const int cb = boxes_per_chunk(P, P.r);
+        const int64_t wmax = static_cast<int64_t>(cb) * P.r;
+        double* Om = tmp.plain(P.n * wmax);
+        double* Yc = tmp.plain(P.n * wmax);
+        for (int side = 0; side < 2; ++side) {
+            for (int i0 = 0; i0 < P.b; i0 += cb) {
+                const int i1 = std::min(P.b, i0 + cb);
+                launch_expand_masked(P, t, side ? H : G, i0, i1, Om, s);
+                op_apply(o, side, static_cast<int64_t>(i1 - i0) * P.r, Om, P.n, Yc, P.n, s);
+                launch_take_box_rows(P, t, Yc, i0, i1, side ? SZ : SY, s);
+            }
+        }
+        if (keep_samples) {
+            for (int side = 0; side < 2; ++side) {
+                double*& dst = side ? h->SZ : h->SY;
+                dst = dalloc_sync(P.n * P.r);
+                HIPC(hipMemcpyAsync(dst, side ? SZ : SY, P.n * P.r * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s));
+            }
+        }
+        mark(1);
+        launch_orth2(P, t, SY, SZ, h->U, h->V, nullptr, nullptr, s);
+        mark(2);
+        cores_any(o, P, t, h->U, h->V, h->Atil, s, tmp);
+        mark(3);
+        nearfield_any(o, P, t, h->U, h->V, h->Atil, h->B, s, tmp);
+        mark(4);
+        if (timing) {
+            double* flag = tmp.get(1);
+            const double* arrs[4] = {h->U, h->V, h->Atil, h->B};
+            const int64_t cnts[4] = {P.n * P.k, P.n * P.k, bk * bk, P.b_values};
+            launch_flag_nonfinite(arrs, cnts, 4, flag, s);
+            double hflag = 0.0;
+            HIPC(hipMemcpyAsync(&hflag, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (hflag != 0.0)
+                fail(BLR_ERR_NUMERICAL, "non-finite values in the compressed operator (samples, bases, cores or near field)");
+            float ms[4];
+            for (int q = 0; q < 4; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+            float tot;
+            HIPC(hipEventElapsedTime(&tot, ev[0], ev[4]));
+            std::memset(rep, 0, sizeof(*rep));
+            rep->ms_sketch = ms[0];
+            rep->ms_orth = ms[1];
+            rep->ms_cores = ms[2];
+            rep->ms_nearfield = ms[3];
+            rep->ms_total = tot;
+            const int64_t br = static_cast<int64_t>(P.b) * P.r;
+            rep->applies_A = br + bk + static_cast<int64_t>(P.ncol) * P.m_max;
+            rep->applies_At = br;
+            rep->sketch_flops = 4.0 * static_cast<double>(P.n) * static_cast<double>(P.n) * static_cast<double>(br);
+            rep->precision = BLR_PREC_FP64;
+        }
+        auto* hh = new blr_ublr;
+        hh->d = std::move(h);
+        *out = hh;
+    });
+}
+
 void blr_ublr_destroy(blr_ublr* h) { delete h; }
 
 blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count) {

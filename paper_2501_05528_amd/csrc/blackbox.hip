@@ -45,6 +45,34 @@ __global__ __launch_bounds__(256) void k_embed_blockdiag(const double* __restric
     X[idx] = rb[row] == j ? S[row + static_cast<int64_t>(t) * n] : 0.0;
 }
 
+// Om(row, (i - i0) r + c) = G(row, c) unless box(row) is a neighbour of box i, for
+// boxes i0 <= i < i1: a column chunk of the masked test matrices of Alg. 3.
+__global__ __launch_bounds__(256) void k_expand_masked(const double* __restrict__ G, int64_t n, int r,
+                                                       const int32_t* __restrict__ rb,
+                                                       const uint8_t* __restrict__ nearm, int nbox, int i0,
+                                                       int i1, double* __restrict__ Om) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t ncols = static_cast<int64_t>(i1 - i0) * r;
+    if (idx >= n * ncols) return;
+    const int64_t col = idx / n;
+    const int64_t row = idx - col * n;
+    const int i = i0 + static_cast<int>(col / r), c = static_cast<int>(col % r);
+    Om[idx] = nearm[static_cast<int64_t>(i) * nbox + rb[row]] ? 0.0 : G[row + static_cast<int64_t>(c) * n];
+}
+
+// S(row, c) = Yc(row, (box(row) - i0) r + c) for the rows of boxes i0 <= i < i1: each
+// box keeps its own rows of the product with its own masked test matrix (Alg. 3).
+__global__ __launch_bounds__(256) void k_take_box_rows(const double* __restrict__ Yc, int64_t n, int r,
+                                                       const int32_t* __restrict__ rb, int64_t row0,
+                                                       int64_t nrows, int i0, double* __restrict__ S) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= nrows * r) return;
+    const int64_t c = idx / nrows;
+    const int64_t row = row0 + (idx - c * nrows);
+    const int64_t q = rb[row] - i0;
+    S[row + c * n] = Yc[row + (q * r + c) * n];
+}
+
 // X_c(box_ptr[l] + u, u) = 1 for every box l of colour c and u < m_l, zero elsewhere
 // (the sparse identity probe of Table 1 step 3), N x m_max.
 __global__ __launch_bounds__(256) void k_identity_probe(int64_t n, int m_max, const int32_t* __restrict__ rb,
@@ -154,6 +182,23 @@ void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const doub
     hipLaunchKernelGGL(k_embed_blockdiag, dim3(blocks_for(total)), dim3(256), 0, s, S, P.n, w, t.row_box,
                        j0, j1, X);
     check_launch_bb("block-diagonal test columns");
+}
+
+void launch_expand_masked(const PlanData& P, const DeviceTables& t, const double* G, int i0, int i1,
+                          double* Om, hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(i1 - i0) * P.r;
+    hipLaunchKernelGGL(k_expand_masked, dim3(blocks_for(total)), dim3(256), 0, s, G, P.n, P.r, t.row_box,
+                       t.nearm, P.b, i0, i1, Om);
+    check_launch_bb("masked test matrices");
+}
+
+void launch_take_box_rows(const PlanData& P, const DeviceTables& t, const double* Yc, int i0, int i1,
+                          double* S, hipStream_t s) {
+    const int64_t row0 = P.box_ptr[i0], nrows = P.box_ptr[i1] - P.box_ptr[i0];
+    const int64_t total = nrows * P.r;
+    hipLaunchKernelGGL(k_take_box_rows, dim3(blocks_for(total)), dim3(256), 0, s, Yc, P.n, P.r, t.row_box,
+                       row0, nrows, i0, S);
+    check_launch_bb("per-box sample rows");
 }
 
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s) {

@@ -87,6 +87,12 @@ void launch_expand_tagged(const PlanData& P, const DeviceTables& t, const double
                           hipStream_t s);
 void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const double* S, int w, int j0,
                             int j1, double* X, hipStream_t s);
+// Alg. 3 on a black box: masked test matrices of boxes [i0, i1) (N x (i1 - i0) r) and
+// each box's own rows of their products.
+void launch_expand_masked(const PlanData& P, const DeviceTables& t, const double* G, int i0, int i1,
+                          double* Om, hipStream_t s);
+void launch_take_box_rows(const PlanData& P, const DeviceTables& t, const double* Yc, int i0, int i1,
+                          double* S, hipStream_t s);
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s);
 void launch_cores_from_w(const PlanData& P, const DeviceTables& t, const double* U, const double* W,
                          int j0, int j1, double* Atil, hipStream_t s);
