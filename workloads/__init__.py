@@ -68,7 +68,7 @@ class Geometry:
 
     @property
     def nboxes(self) -> int:
-        return int(self.lattice.shape[0])
+        return len(self.box_ptr) - 1
 
     def box_sizes(self) -> np.ndarray:
         return np.diff(self.box_ptr)
@@ -266,3 +266,46 @@ def irregular_grid_geometry(widths_per_axis, jitter: float = 0.0, seed: int = 0)
         pts = pts + jitter * rng(seed, STREAM_JITTER).uniform(-1.0, 1.0, size=pts.shape) * h[None, :]
     box_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     return Geometry(dim, np.ascontiguousarray(pts), box_ptr, lattice, tuple(B), tuple(0 for _ in B))
+
+
+STREAM_POINTS = 10
+
+
+def kd_geometry(n: int, dim: int, levels: int, seed: int):
+    """Uniformly random points in [0,1]^dim tessellated by median splits.
+
+    The unit cube is halved ``levels`` times, cycling through the axes; each cut
+    lies midway between the two middle points of the cell along that axis, so
+    the 2^levels boxes hold n / 2^levels points each, up to one (the geometry of
+    Section 7: the domain is subdivided until every box reaches the desired
+    cardinality).  Boxes are numbered in tree order and rows are box-major.
+
+    Returns (Geometry with ``lattice`` None, near lists, cells) where ``cells``
+    is (b, dim, 2) with the closed [lo, hi] range of every box per axis and
+    ``near[i]`` lists, ascending, every box whose cell shares a boundary point
+    with box i's (box i included, Section 2.5).
+    """
+    pts0 = rng(seed, STREAM_POINTS).uniform(0.0, 1.0, size=(n, dim))
+    boxes = [(np.arange(n), np.array([[0.0, 1.0]] * dim))]
+    for lev in range(levels):
+        ax = lev % dim
+        nxt = []
+        for idx, cell in boxes:
+            order = idx[np.argsort(pts0[idx, ax], kind="stable")]
+            h = len(order) // 2
+            cut = 0.5 * (pts0[order[h - 1], ax] + pts0[order[h], ax])
+            lo_cell, hi_cell = cell.copy(), cell.copy()
+            lo_cell[ax, 1] = cut
+            hi_cell[ax, 0] = cut
+            nxt += [(order[:h], lo_cell), (order[h:], hi_cell)]
+        boxes = nxt
+    pts = np.concatenate([pts0[idx] for idx, _ in boxes], axis=0)
+    box_ptr = np.concatenate([[0], np.cumsum([len(idx) for idx, _ in boxes])]).astype(np.int64)
+    cells = np.stack([cell for _, cell in boxes])
+    b = len(boxes)
+    near = []
+    for i in range(b):
+        touch = np.all((cells[:, :, 0] <= cells[i, :, 1]) & (cells[i, :, 0] <= cells[:, :, 1]), axis=1)
+        near.append([int(j) for j in np.flatnonzero(touch)])
+    geom = Geometry(dim, np.ascontiguousarray(pts), box_ptr, None, (b,), (0,))
+    return geom, near, cells
