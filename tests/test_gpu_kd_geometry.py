@@ -1,0 +1,109 @@
+"""GPU parity on the geometry of the paper's experiments (Section 7): uniformly random
+points, a median-split tessellation (box sizes differ by up to one), neighbours = boxes
+whose cells share a boundary (caller neighbour lists, greedy probe colours, no lattice).
+
+* Tagging (Alg. 2 + Table 1) with the built-in kernel operator: sketches to 1e-12 of their
+  largest entry, every reconstructed block to 1e-11 max|A|, relative Frobenius error in the
+  1.5 band of the oracle's, and the product count 2 ell r + b k + (colours) m_max.
+* Alg. 3 on the same geometry and operator: per-box samples to 1e-12, blocks to 1e-11.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+CASES = {
+    # name: (n, dim, levels, kernel, k, p, seed)
+    "log2d_n8100": (8100, 2, 6, "log", 16, 10, 20250106),
+    "invr3d_n5000": (5000, 3, 6, "inv_r", 12, 10, 20250107),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def run(request):
+    import torch
+    import paper_2501_05528_amd as P
+    n, dim, levels, kind, k, p, seed = CASES[request.param]
+    g, near, _ = W.kd_geometry(n, dim, levels, seed)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(seed, g.nboxes, ell)
+    G, H = W.gaussian_test_blocks(seed, g.n, k + p)
+    A = O.KernelOperator(kind, g.pts).block()
+    op_o = O.DenseOperator(A)
+    res = O.reconstruct_tag(op_o, g.box_ptr, None, k, p, 3, T, G, H, near=near)
+    res["err"] = O.rel_fro_error(op_o, res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, k)
+    bres = O.reconstruct_basic(op_o, g.box_ptr, None, k, p, G, H, near=near)
+    _announce(f"kd geometry {request.param}: N={g.n} b={g.nboxes} k={k} ell={ell}")
+    plan = P.Plan(g.box_ptr, None, k, T, p=p, extra_tag_cols=3, near=near)
+    op = P.Operator.kernel(kind, g.pts)
+    Gd, Hd = P.colmajor(G), P.colmajor(H)
+    h, rep = P.compress(plan, op, Gd, Hd, keep_intermediates=True)
+    hb, _ = P.basic_compress(plan, op, Gd, Hd, keep_samples=True)
+    torch.cuda.synchronize()
+    return dict(g=g, A=A, k=k, near=near, res=res, bres=bres, plan=plan, op=op, h=h, hb=hb, rep=rep,
+                name=request.param)
+
+
+def _worst_block(run, h, res):
+    g, k = run["g"], run["k"]
+    bp = g.box_ptr
+    U, V, At = (h.part(x).cpu().numpy() for x in ("U", "V", "Atil"))
+    Bflat = h.part("B").cpu().numpy()[:, 0]
+    near_ptr, near_idx, _, boff = run["plan"].lists()
+    Amax = np.max(np.abs(run["A"]))
+    worst = 0.0
+    for i in range(g.nboxes):
+        nb = {int(near_idx[q]): int(boff[q]) for q in range(near_ptr[i], near_ptr[i + 1])}
+        for j in range(g.nboxes):
+            ri, cj = slice(bp[i], bp[i + 1]), slice(bp[j], bp[j + 1])
+            rg = U[ri] @ At[i * k:(i + 1) * k, j * k:(j + 1) * k] @ V[cj].T
+            ro = res["U"][ri] @ res["Atil"][i * k:(i + 1) * k, j * k:(j + 1) * k] @ res["V"][cj].T
+            if j in nb:
+                mi, mj = bp[i + 1] - bp[i], bp[j + 1] - bp[j]
+                rg = rg + Bflat[nb[j]:nb[j] + mi * mj].reshape((mi, mj), order="F")
+                ro = ro + res["B"][(i, j)]
+            worst = max(worst, np.max(np.abs(rg - ro)) / Amax)
+    return worst
+
+
+def test_lists_and_counts(run):
+    _, near_idx, colour, _ = run["plan"].lists()
+    assert near_idx.tolist() == [j for nb in run["near"] for j in nb]
+    assert colour.tolist() == run["res"]["colour"].tolist()
+    plan, g = run["plan"], run["g"]
+    m = int(np.max(g.box_sizes()))
+    assert run["rep"]["applies_A"] == plan.ell * plan.r + g.nboxes * run["k"] + plan.info["ncolours"] * m
+    assert run["rep"]["applies_At"] == plan.ell * plan.r
+
+
+def test_tagging_vs_oracle(run):
+    h, res = run["h"], run["res"]
+    for name in ("Y", "Z", "Yhat", "Zhat"):
+        got = h.part(name).cpu().numpy()
+        assert np.max(np.abs(got - res[name])) <= 1e-12 * np.max(np.abs(res[name])), name
+    worst = _worst_block(run, h, res)
+    assert worst <= 1e-11, worst
+
+
+def test_tagging_error_band(run):
+    e_gpu = run["h"].error_fro(run["op"])
+    e_or = run["res"]["err"]
+    _announce(f"{run['name']}: rel fro error gpu {e_gpu:.3e} oracle {e_or:.3e}")
+    assert (abs(e_gpu - e_or) <= 1e-12) or (1 / 1.5 <= e_gpu / e_or <= 1.5)
+
+
+def test_basic_vs_oracle(run):
+    hb, bres = run["hb"], run["bres"]
+    for name in ("SY", "SZ"):
+        got = hb.part(name).cpu().numpy()
+        assert np.max(np.abs(got - bres[name])) <= 1e-12 * np.max(np.abs(bres[name])), name
+    worst = _worst_block(run, hb, bres)
+    assert worst <= 1e-11, worst
