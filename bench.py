@@ -172,6 +172,43 @@ def basic_section(S, tag_value, with_error):
             "sample_TFLOPs": round(sk, 2), "sample_flops": rep["sketch_flops"]}
 
 
+def paper_geometry_section(cases=((20000, 6), (100000, 7)), k=50, p=10, steps=3, seed=20250108):
+    """The geometry of the paper's experiments (Section 7): N uniformly random points in the
+    unit square, median-split boxes (b = 64 and 128 for N = 20000 and 100000, close to the
+    paper's b = sqrt(9 N / k) at k = 30), neighbours sharing a boundary, log kernel, k = 50 (for
+    errors near 1e-8), FP64."""
+    import torch
+    import paper_2501_05528_amd as P
+    out = {}
+    for n, levels in cases:
+        g, near, _ = W.kd_geometry(n, 2, levels, seed)
+        ell = P.tag_columns(g.box_ptr, None, 3, near=near)
+        T = W.tag_matrix(seed, g.nboxes, ell)
+        G, H = W.gaussian_test_blocks(seed, g.n, k + p)
+        plan = P.Plan(g.box_ptr, None, k, T, p=p, extra_tag_cols=3, near=near)
+        op = P.Operator.kernel("log", g.pts)
+        Gd, Hd = P.colmajor(G), P.colmajor(H)
+        h, _ = P.compress(plan, op, Gd, Hd, report=True)
+        del h
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h, rep = P.compress(plan, op, Gd, Hd, report=True)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        err = h.error_fro(op)
+        sizes = g.box_sizes()
+        log(f"paper geometry N={n}: {1e3 * el:.1f} ms, rel err {err:.2e}")
+        out[f"n{n}"] = {"value": round(1.0 / el, 4), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 3),
+                        "boxes": g.nboxes, "m_min": int(sizes.min()), "m_max": int(sizes.max()), "ell": ell,
+                        "ncolours": plan.info["ncolours"],
+                        "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+                        "rel_err_fro": err,
+                        "sketch_TFLOPs": round(rep["sketch_flops"] / (rep["ms_sketch"] * 1e-3) / 1e12, 2)}
+        del h, plan, op
+    return out
+
+
 def cpu_baseline(S, nsample_boxes=4):
     """The oracle, as it stands, on a bounded sample: every stage of reconstruct_tag
     restricted to `nsample_boxes` row boxes (sketch rows, their post-processing and
@@ -359,6 +396,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-job measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-paper-geometry", action="store_true",
+                    help="skip the random-point geometry measurement")
     ap.add_argument("--no-basic", action="store_true",
                     help="skip the one-off Alg. 3 (basic randomized SVD) comparison run")
     ap.add_argument("--no-mixed", action="store_true",
@@ -442,6 +481,12 @@ def main():
                                     "algorithmic_flops_per_launch": rp["refine_flops"]},
             }
         out["mixed"] = mixed
+    if not args.no_paper_geometry:
+        try:
+            log("random-point geometry of the paper's experiments")
+            out["paper_geometry"] = paper_geometry_section()
+        except Exception as e:  # extra measurement: never lose the line
+            out["paper_geometry"] = {"error": repr(e)}
     if not args.no_basic:
         try:
             log("Alg. 3 comparison (basic randomized SVD per box)")
