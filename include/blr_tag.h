@@ -384,6 +384,30 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
 blr_status blr_basic_compress(const blr_plan* plan, const blr_operator* op, const double* G,
                               const double* H, int32_t keep_samples, void* stream, blr_ublr** out,
                               blr_report* rep);
+
+/*
+ * Alg. 1 (block nullification for basis construction) followed by steps
+ * (II)-(III) of Table 1: the method tagging improves on (Section 3).  One
+ * sketch Y = A Omega, Z = A* Psi on s columns; for every box i, P^(i) = r
+ * orthonormal vectors of null(Omega^(i)), where Omega^(i) stacks the rows of
+ * the neighbour boxes (ascending box order), taken from the Householder QR of
+ * Omega^(i)* (reflector signs that avoid cancellation; P^(i) = the r columns of
+ * the orthogonal factor after its first |rows of N_i| columns); U_i = the
+ * top-k left singular vectors of Y(I_i,:) P^(i), V_i likewise from Z and Psi.
+ * Omega and Psi: device, N x s column-major, ld N; s >= blr_bn_min_columns
+ * (r plus the rows of the largest neighbourhood, i.e. r + 3^d m on a uniform
+ * tessellation) or BLR_ERR_INVALID_ARG.  The null vectors are computed on the
+ * host from copies of Omega and Psi (the call synchronises the stream there);
+ * a rank-deficient neighbour block gives BLR_ERR_NUMERICAL.  Report: applies_A
+ * = s + b k + (colours) m_max, applies_At = s; ms_sketch covers the two
+ * sketches, ms_postprocess the copies, null vectors and projections.
+ * keep_samples != 0 keeps Y(I_i,:) P^(i) and Z(I_i,:) Q^(i) as BLR_PART_SY /
+ * BLR_PART_SZ.  Ownership and errors as for blr_tag_compress (FP64, any operator).
+ */
+blr_status blr_bn_min_columns(const blr_plan* plan, int64_t* s);
+blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t s, const double* Omega,
+                           const double* Psi, int32_t keep_samples, void* stream, blr_ublr** out,
+                           blr_report* rep);
 void blr_ublr_destroy(blr_ublr* h);
 
 /* Which device array of a compressed handle. */

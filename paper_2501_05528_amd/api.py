@@ -443,6 +443,28 @@ def basic_compress(plan: Plan, op: Operator, G, H, keep_samples: bool = False, r
     return out, rd
 
 
+def bn_min_columns(plan: Plan) -> int:
+    """The smallest test-matrix width s for block nullification (Alg. 1) on ``plan``."""
+    v = ctypes.c_int64()
+    check(lib().blr_bn_min_columns(plan._h, byref(v)))
+    return v.value
+
+
+def bn_compress(plan: Plan, op: Operator, Omega, Psi, keep_samples: bool = False, report: bool = True,
+                stream=None):
+    """Alg. 1 (block nullification) for step (I), then steps (II)-(III) of Table 1.
+    Omega and Psi: N x s column-major CUDA float64 with s >= bn_min_columns(plan).
+    Returns (UBLR, report dict or None); keep_samples keeps parts "SY", "SZ"."""
+    h = c_void_p()
+    rep = _lib.Report()
+    check(lib().blr_bn_compress(plan._h, op._h, Omega.shape[1], _ptr(Omega), _ptr(Psi),
+                                1 if keep_samples else 0, _stream(stream), byref(h),
+                                byref(rep) if report else None))
+    out = UBLR(h, plan)
+    rd = {f: getattr(rep, f) for f, _ in _lib.Report._fields_} if report else None
+    return out, rd
+
+
 # ---------------------------------------------------------------- stages
 def sketch(plan: Plan, op: Operator, G, H, stream=None):
     LR = plan.ell * plan.r

@@ -921,6 +921,125 @@ blr_status blr_basic_compress(const blr_plan* plan, const blr_operator* op, cons
     });
 }
 
+blr_status blr_bn_min_columns(const blr_plan* plan, int64_t* s) {
+    return guard([&] {
+        if (!s) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        *s = bn_min_columns(plan_of(plan));
+    });
+}
+
+blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t s, const double* Omega,
+                           const double* Psi, int32_t keep_samples, void* stream, blr_ublr** out,
+                           blr_report* rep) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!Omega || !Psi) fail(BLR_ERR_INVALID_ARG, "NULL Omega or Psi");
+        if (s < bn_min_columns(P))
+            fail(BLR_ERR_INVALID_ARG, "s must be at least r plus the rows of the largest neighbourhood");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = plan->d->tables();
+        const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+        const int64_t ns = P.n * s;
+
+        auto h = std::make_unique<UblrData>();
+        h->plan = plan->d;
+        h->device = current_device();
+        h->precision = BLR_PREC_FP64;
+        h->U = dalloc_sync(P.n * P.k);
+        h->V = dalloc_sync(P.n * P.k);
+        h->Atil = dalloc_sync(bk * bk);
+        h->B = dalloc_sync(P.b_values);
+        AsyncTemps tmp(st);
+        double* SY = tmp.get(P.n * P.r);
+        double* SZ = tmp.get(P.n * P.r);
+        double* Y = tmp.plain(ns);
+        double* Z = tmp.plain(ns);
+        double* dP = tmp.plain(static_cast<int64_t>(P.b) * s * P.r);
+        double* dQ = tmp.plain(static_cast<int64_t>(P.b) * s * P.r);
+
+        const bool timing = rep != nullptr;
+        struct Events {
+            hipEvent_t e[6] = {};
+            ~Events() {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } evs;
+        hipEvent_t* ev = evs.e;
+        if (timing)
+            for (int q = 0; q < 6; ++q) HIPC(hipEventCreate(&ev[q]));
+        auto mark = [&](int q) {
+            if (timing) HIPC(hipEventRecord(ev[q], st));
+        };
+        // events: 0 start | 1 sketches | 2 null vectors + projection | 3 bases | 4 cores | 5 near field
+        mark(0);
+        op_apply(o, 0, s, Omega, P.n, Y, P.n, st);
+        op_apply(o, 1, s, Psi, P.n, Z, P.n, st);
+        mark(1);
+        {
+            // the null vectors depend on the test matrices only: host Householder QRs
+            std::vector<double> hOm(static_cast<size_t>(ns)), hNull(static_cast<size_t>(P.b) * s * P.r);
+            for (int side = 0; side < 2; ++side) {
+                HIPC(hipMemcpyAsync(hOm.data(), side ? Psi : Omega, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPC(hipStreamSynchronize(st));
+                bn_null_vectors(P, hOm.data(), s, hNull.data());
+                HIPC(hipMemcpyAsync(side ? dQ : dP, hNull.data(), hNull.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, st));
+                HIPC(hipStreamSynchronize(st));
+            }
+        }
+        launch_bn_project(P, t, Y, s, dP, SY, st);
+        launch_bn_project(P, t, Z, s, dQ, SZ, st);
+        if (keep_samples) {
+            for (int side = 0; side < 2; ++side) {
+                double*& dst = side ? h->SZ : h->SY;
+                dst = dalloc_sync(P.n * P.r);
+                HIPC(hipMemcpyAsync(dst, side ? SZ : SY, P.n * P.r * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+            }
+        }
+        mark(2);
+        launch_orth2(P, t, SY, SZ, h->U, h->V, nullptr, nullptr, st);
+        mark(3);
+        cores_any(o, P, t, h->U, h->V, h->Atil, st, tmp);
+        mark(4);
+        nearfield_any(o, P, t, h->U, h->V, h->Atil, h->B, st, tmp);
+        mark(5);
+        if (timing) {
+            double* flag = tmp.get(1);
+            const double* arrs[4] = {h->U, h->V, h->Atil, h->B};
+            const int64_t cnts[4] = {P.n * P.k, P.n * P.k, bk * bk, P.b_values};
+            launch_flag_nonfinite(arrs, cnts, 4, flag, st);
+            double hflag = 0.0;
+            HIPC(hipMemcpyAsync(&hflag, flag, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            if (hflag != 0.0)
+                fail(BLR_ERR_NUMERICAL, "non-finite values in the compressed operator (samples, bases, cores or near field)");
+            float ms[5];
+            for (int q = 0; q < 5; ++q) HIPC(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+            float tot;
+            HIPC(hipEventElapsedTime(&tot, ev[0], ev[5]));
+            std::memset(rep, 0, sizeof(*rep));
+            rep->ms_sketch = ms[0];
+            rep->ms_postprocess = ms[1];
+            rep->ms_orth = ms[2];
+            rep->ms_cores = ms[3];
+            rep->ms_nearfield = ms[4];
+            rep->ms_total = tot;
+            rep->applies_A = s + bk + static_cast<int64_t>(P.ncol) * P.m_max;
+            rep->applies_At = s;
+            rep->sketch_flops = 4.0 * static_cast<double>(P.n) * static_cast<double>(P.n) * static_cast<double>(s);
+            rep->precision = BLR_PREC_FP64;
+        }
+        auto* hh = new blr_ublr;
+        hh->d = std::move(h);
+        *out = hh;
+    });
+}
+
 void blr_ublr_destroy(blr_ublr* h) { delete h; }
 
 blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count) {

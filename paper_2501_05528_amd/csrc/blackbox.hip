@@ -73,6 +73,21 @@ __global__ __launch_bounds__(256) void k_take_box_rows(const double* __restrict_
     S[row + c * n] = Yc[row + (q * r + c) * n];
 }
 
+// S(row, c) = sum_t Y(row, t) P_box(row)(t, c): each box's rows of the sketch times its
+// own null vectors (Alg. 1), Y N x s, P b x (s x r) column-major blocks.
+__global__ __launch_bounds__(256) void k_bn_project(const double* __restrict__ Y, int64_t n, int64_t s, int r,
+                                                    const int32_t* __restrict__ rb,
+                                                    const double* __restrict__ Pall, double* __restrict__ S) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= n * r) return;
+    const int64_t c = idx / n;
+    const int64_t row = idx - c * n;
+    const double* P = Pall + static_cast<int64_t>(rb[row]) * s * r + c * s;
+    double acc = 0.0;
+    for (int64_t t = 0; t < s; ++t) acc = fma(Y[row + t * n], P[t], acc);
+    S[row + c * n] = acc;
+}
+
 // X_c(box_ptr[l] + u, u) = 1 for every box l of colour c and u < m_l, zero elsewhere
 // (the sparse identity probe of Table 1 step 3), N x m_max.
 __global__ __launch_bounds__(256) void k_identity_probe(int64_t n, int m_max, const int32_t* __restrict__ rb,
@@ -199,6 +214,14 @@ void launch_take_box_rows(const PlanData& P, const DeviceTables& t, const double
     hipLaunchKernelGGL(k_take_box_rows, dim3(blocks_for(total)), dim3(256), 0, s, Yc, P.n, P.r, t.row_box,
                        row0, nrows, i0, S);
     check_launch_bb("per-box sample rows");
+}
+
+void launch_bn_project(const PlanData& P, const DeviceTables& t, const double* Y, int64_t ns,
+                       const double* Pall, double* S, hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(P.r);
+    hipLaunchKernelGGL(k_bn_project, dim3(blocks_for(total)), dim3(256), 0, s, Y, P.n, ns, P.r, t.row_box,
+                       Pall, S);
+    check_launch_bb("block-nullified samples");
 }
 
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s) {

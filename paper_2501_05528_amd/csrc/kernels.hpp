@@ -93,6 +93,9 @@ void launch_expand_masked(const PlanData& P, const DeviceTables& t, const double
                           double* Om, hipStream_t s);
 void launch_take_box_rows(const PlanData& P, const DeviceTables& t, const double* Yc, int i0, int i1,
                           double* S, hipStream_t s);
+// Alg. 1: S(row, :) = Y(row, :) P_box(row) with Y N x ns and P b blocks of ns x r.
+void launch_bn_project(const PlanData& P, const DeviceTables& t, const double* Y, int64_t ns,
+                       const double* Pall, double* S, hipStream_t s);
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s);
 void launch_cores_from_w(const PlanData& P, const DeviceTables& t, const double* U, const double* W,
                          int j0, int j1, double* Atil, hipStream_t s);
