@@ -209,6 +209,53 @@ def paper_geometry_section(cases=((20000, 6), (100000, 7)), k=50, p=10, steps=3,
     return out
 
 
+def bn_section(cases=((8, 8), (16, 16)), q=8, k=16, p=10, seed=20250109):
+    """Alg. 1 (block nullification) against tagging on 2D log-kernel grids of boxes of
+    q x q = 64 points (k = 16), with the same plan and operator: products, time and
+    error.  Block nullification sketches s = r + 9 m columns per side and needs a
+    Householder QR of an s x (up to 9 m) block of the test matrix per box and side
+    (host FP64, the post-processing cost of Section 3.2)."""
+    import torch
+    import paper_2501_05528_amd as P
+    out = {}
+    for bx, by in cases:
+        g = W.grid_geometry(2, (bx, by), q)
+        ell = P.tag_columns(g.box_ptr, g.lattice, 3)
+        T = W.tag_matrix(seed, g.nboxes, ell)
+        plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
+        op = P.Operator.kernel("log", g.pts)
+        s = P.bn_min_columns(plan)
+        Om, Ps = (P.colmajor(a) for a in W.gaussian_test_blocks(seed, g.n, s))
+        G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(seed, g.n, k + p))
+        h, _ = P.compress(plan, op, G, H, report=True)
+        del h
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, rt = P.compress(plan, op, G, H, report=True)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        et = h.error_fro(op)
+        del h
+        t0 = time.perf_counter()
+        h, rb = P.bn_compress(plan, op, Om, Ps, report=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        eb = h.error_fro(op)
+        del h
+        log(f"bn N={g.n}: {1e3 * tb:.1f} ms (post-processing {rb['ms_postprocess']:.1f} ms) "
+            f"vs tagging {1e3 * tt:.1f} ms")
+        out[f"n{g.n}"] = {
+            "boxes": g.nboxes, "m": q * q, "k": k, "s": s, "ell": ell,
+            "bn": {"ms_per_step": round(1e3 * tb, 3), "applies_per_compression": int(rb["applies_A"] + rb["applies_At"]),
+                   "ms_sketch": round(rb["ms_sketch"], 3), "ms_postprocess": round(rb["ms_postprocess"], 3),
+                   "rel_err_fro": eb},
+            "tagging": {"ms_per_step": round(1e3 * tt, 3), "applies_per_compression": int(rt["applies_A"] + rt["applies_At"]),
+                        "ms_sketch": round(rt["ms_sketch"], 3), "ms_postprocess": round(rt["ms_postprocess"], 3),
+                        "rel_err_fro": et},
+            "tagging_speedup": round(tb / tt, 2)}
+    return out
+
+
 def cpu_baseline(S, nsample_boxes=4):
     """The oracle, as it stands, on a bounded sample: every stage of reconstruct_tag
     restricted to `nsample_boxes` row boxes (sketch rows, their post-processing and
@@ -398,6 +445,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-paper-geometry", action="store_true",
                     help="skip the random-point geometry measurement")
+    ap.add_argument("--no-bn", action="store_true",
+                    help="skip the block-nullification (Alg. 1) comparison")
     ap.add_argument("--no-basic", action="store_true",
                     help="skip the one-off Alg. 3 (basic randomized SVD) comparison run")
     ap.add_argument("--no-mixed", action="store_true",
@@ -487,6 +536,12 @@ def main():
             out["paper_geometry"] = paper_geometry_section()
         except Exception as e:  # extra measurement: never lose the line
             out["paper_geometry"] = {"error": repr(e)}
+    if not args.no_bn:
+        try:
+            log("Alg. 1 comparison (block nullification)")
+            out["bn_alg1"] = bn_section()
+        except Exception as e:  # extra measurement: never lose the line
+            out["bn_alg1"] = {"error": repr(e)}
     if not args.no_basic:
         try:
             log("Alg. 3 comparison (basic randomized SVD per box)")
