@@ -6,7 +6,8 @@
 * Against the oracle on the same G, H: each box's own rows of its two samples to
   1e-12 of their largest entry; every far block U_i Atil_ij V_j* and near block
   plus B_ij to 1e-11 max|A|.
-* A planted exact-rank uBLR matrix is recovered to 1e-12 (relative Frobenius).
+* Exact relative Frobenius error: <= 1e-12 on a planted exact-rank uBLR matrix, else
+  within a factor 1.5 of the oracle's.
 """
 import numpy as np
 import pytest
@@ -112,8 +113,17 @@ def test_blocks_vs_oracle(run):
     assert worst <= 1e-11, worst
 
 
-def test_planted_exact_recovery(run):
-    if run["name"] != "planted" or run["cols"] is not None:
-        pytest.skip("exact recovery holds for the planted exact-rank matrix; the exact error "
-                    "needs entry access, which a black-box operator does not give")
-    assert run["h"].error_fro(run["op"]) <= 1e-12
+def test_error_fro(run):
+    """Exact relative Frobenius error: <= 1e-12 for the planted exact-rank matrix, else in
+    the 1.5 band of the oracle's error on the same inputs."""
+    if run["cols"] is not None:
+        pytest.skip("the exact error needs entry access, which a black-box operator does not give")
+    e_gpu = run["h"].error_fro(run["op"])
+    if run["name"] == "planted":
+        assert e_gpu <= 1e-12
+        return
+    res = run["res"]
+    e_or = O.rel_fro_error(O.DenseOperator(run["A"]), res["U"], res["V"], res["Atil"], res["B"],
+                           run["g"].box_ptr, run["k"])
+    _announce(f"{run['name']}: rel fro error gpu {e_gpu:.3e} oracle {e_or:.3e}")
+    assert (abs(e_gpu - e_or) <= 1e-12) or (1 / 1.5 <= e_gpu / e_or <= 1.5)
