@@ -408,6 +408,24 @@ blr_status blr_bn_min_columns(const blr_plan* plan, int64_t* s);
 blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t s, const double* Omega,
                            const double* Psi, int32_t keep_samples, void* stream, blr_ublr** out,
                            blr_report* rep);
+
+/*
+ * Tolerance-driven choice of the uniform rank (Section 2.3: the range finder
+ * can pick its rank from a tolerance; Section 6: larger ranks can be chosen and
+ * truncated as needed).  One tagged sketch and post-processing at the plan's
+ * r = k + p columns (Alg. 2), then the singular values of every box's m_i x r
+ * samples Yhat_i and Zhat_i.  *k_out = the largest over boxes and sides of
+ * #{j : sigma_j(box) > tol * the largest singular value of that side over all
+ * boxes}: the smallest uniform rank that keeps every such direction.  *k_out
+ * = r means the tolerance was not reached within the sample (plan again with
+ * a larger k); a plan with rank *k_out then compresses at that accuracy.
+ * G, H as for blr_tag_compress.  sigma: optional host array 2 x b x r
+ * (Y side then Z side, each box's values descending).  Synchronises the
+ * stream; tol < 0 or NaN gives BLR_ERR_INVALID_ARG, non-finite samples
+ * BLR_ERR_NUMERICAL.  Any operator.
+ */
+blr_status blr_tag_rank(const blr_plan* plan, const blr_operator* op, const double* G, const double* H,
+                        double tol, void* stream, int32_t* k_out, double* sigma);
 void blr_ublr_destroy(blr_ublr* h);
 
 /* Which device array of a compressed handle. */

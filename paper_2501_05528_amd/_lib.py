@@ -113,6 +113,8 @@ SIGNATURES = {
     "blr_bn_min_columns": (c_int32, [c_void_p, P_i64]),
     "blr_bn_compress": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int32, c_void_p,
                                   POINTER(c_void_p), POINTER(Report)]),
+    "blr_tag_rank": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, P_i32,
+                               POINTER(c_double)]),
     "blr_ublr_destroy": (None, [c_void_p]),
     "blr_ublr_part_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), P_i64]),
     "blr_ublr_export": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),

@@ -465,6 +465,16 @@ def bn_compress(plan: Plan, op: Operator, Omega, Psi, keep_samples: bool = False
     return out, rd
 
 
+def tag_rank(plan: Plan, op: Operator, G, H, tol: float, stream=None):
+    """Tolerance-driven uniform rank from one tagged sketch at the plan's r columns.
+    Returns (k, sigma) with sigma a 2 x b x r numpy array (Y side, Z side)."""
+    k = c_int32()
+    sig = np.zeros((2, plan.b, plan.r))
+    check(lib().blr_tag_rank(plan._h, op._h, _ptr(G), _ptr(H), float(tol), _stream(stream), byref(k),
+                             sig.ctypes.data_as(ctypes.POINTER(c_double))))
+    return k.value, sig
+
+
 # ---------------------------------------------------------------- stages
 def sketch(plan: Plan, op: Operator, G, H, stream=None):
     LR = plan.ell * plan.r

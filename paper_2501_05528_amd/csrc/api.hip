@@ -1040,6 +1040,53 @@ blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t
     });
 }
 
+blr_status blr_tag_rank(const blr_plan* plan, const blr_operator* op, const double* G, const double* H,
+                        double tol, void* stream, int32_t* k_out, double* sigma) {
+    return guard([&] {
+        if (!k_out) fail(BLR_ERR_INVALID_ARG, "NULL output");
+        const PlanData& P = plan_of(plan);
+        const OpData& o = op_of(op, P);
+        if (!G || !H) fail(BLR_ERR_INVALID_ARG, "NULL G or H");
+        if (!(tol >= 0.0)) fail(BLR_ERR_INVALID_ARG, "tolerance must be a non-negative number");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = plan->d->tables();
+        const int64_t LR = static_cast<int64_t>(P.ell) * P.r;
+        const int64_t br = static_cast<int64_t>(P.b) * P.r;
+        AsyncTemps tmp(st);
+        double* Y = tmp.get(P.n * LR);
+        double* Z = tmp.get(P.n * LR);
+        double* Yh = tmp.get(P.n * P.r);
+        double* Zh = tmp.get(P.n * P.r);
+        double* Q0 = tmp.get(P.n * P.k);
+        double* Q1 = tmp.get(P.n * P.k);
+        double* sig = tmp.get(2 * br);
+        sketch_any(o, P, t, G, H, Y, Z, st, tmp);
+        launch_postprocess(P, t, Y, Yh, st);
+        launch_postprocess(P, t, Z, Zh, st);
+        launch_orth2(P, t, Yh, Zh, Q0, Q1, sig, sig + br, st);
+        std::vector<double> hs(static_cast<size_t>(2 * br));
+        HIPC(hipMemcpyAsync(hs.data(), sig, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        for (double v : hs)
+            if (!std::isfinite(v)) fail(BLR_ERR_NUMERICAL, "non-finite singular values of the tagged samples");
+        // k = max over boxes and sides of #{j : sigma_j(box) > tol * largest sigma of that side}
+        int k = 0;
+        for (int side = 0; side < 2; ++side) {
+            const double* sg = hs.data() + side * br;
+            double top = 0.0;
+            for (int i = 0; i < P.b; ++i) top = std::max(top, sg[static_cast<int64_t>(i) * P.r]);
+            if (top <= 0.0) continue;
+            for (int i = 0; i < P.b; ++i) {
+                int c = 0;
+                for (int j = 0; j < P.r; ++j) c += sg[static_cast<int64_t>(i) * P.r + j] > tol * top ? 1 : 0;
+                k = std::max(k, c);
+            }
+        }
+        *k_out = k;
+        if (sigma) std::memcpy(sigma, hs.data(), hs.size() * sizeof(double));
+    });
+}
+
 void blr_ublr_destroy(blr_ublr* h) { delete h; }
 
 blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count) {

@@ -1,0 +1,74 @@
+"""GPU parity of the tolerance-driven rank choice (blr_tag_rank): the per-box singular
+values of the tagged samples against the oracle's SVDs of its own Yhat_i, Zhat_i (1e-10 of
+each side's largest), and the chosen rank equal to the oracle's wherever no singular value
+lies within 1e-8 (relative) of the threshold; the planted exact rank is found exactly."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOLS = (1e-3, 1e-6, 1e-8, 1e-10)
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _case(name):
+    if name == "planted":
+        wl = W.WORKLOADS["planted_2d_n4096"]
+        g = wl.geometry()
+        A, _, _ = W.planted_exact_rank(g, wl.k, wl.seed)
+        return g, A, wl.k, wl.p, wl.seed
+    if name == "log_ragged":
+        g = W.grid_geometry(2, (6, 5), (15, 13), jitter=0.25, seed=20250112)
+        return g, O.KernelOperator("log", g.pts).block(), 30, 10, 20250112
+    raise KeyError(name)
+
+
+@pytest.fixture(scope="module", params=["planted", "log_ragged"])
+def run(request):
+    import paper_2501_05528_amd as P
+    g, A, k, p, seed = _case(request.param)
+    near = O.near_lists(g.lattice)
+    T = W.tag_matrix(seed, g.nboxes, O.num_tag_columns(near, 3))
+    G, H = W.gaussian_test_blocks(seed, g.n, k + p)
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, k, p, 3, T, G, H, steps=("I",))
+    sy = O.box_singular_values(res["Yhat"], g.box_ptr)
+    sz = O.box_singular_values(res["Zhat"], g.box_ptr)
+    _announce(f"rank {request.param} N={g.n} b={g.nboxes} r={k + p}")
+    plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
+    op = P.Operator.kernel("log", g.pts) if request.param == "log_ragged" else P.Operator.dense(P.colmajor(A))
+    Gd, Hd = P.colmajor(G), P.colmajor(H)
+    got = {tol: P.tag_rank(plan, op, Gd, Hd, tol) for tol in TOLS}
+    return dict(P=P, g=g, A=A, k=k, sy=sy, sz=sz, got=got, plan=plan, op=op, Gd=Gd, Hd=Hd,
+                name=request.param)
+
+
+def test_singular_values_vs_oracle(run):
+    _, sig = run["got"][TOLS[0]]
+    for side, ref in ((0, run["sy"]), (1, run["sz"])):
+        assert np.max(np.abs(sig[side] - ref)) <= 1e-10 * np.max(ref)
+
+
+def test_rank_vs_oracle(run):
+    sy, sz = run["sy"], run["sz"]
+    for tol in TOLS:
+        k_gpu, _ = run["got"][tol]
+        k_or = O.rank_for_tolerance(sy, sz, tol)
+        _announce(f"{run['name']}: tol {tol:.0e} -> k {k_gpu} (oracle {k_or})")
+        near = any(np.any(np.abs(s - tol * s[:, 0].max()) <= 1e-8 * tol * s[:, 0].max()) for s in (sy, sz))
+        if not near:
+            assert k_gpu == k_or
+    if run["name"] == "planted":
+        assert all(run["got"][tol][0] == run["k"] for tol in TOLS[1:])
+
+
+def test_invalid_tolerance(run):
+    P = run["P"]
+    with pytest.raises(P.BlrError) as ei:
+        P.tag_rank(run["plan"], run["op"], run["Gd"], run["Hd"], -1.0)
+    assert ei.value.name == "BLR_ERR_INVALID_ARG"
