@@ -256,6 +256,30 @@ def bn_section(cases=((8, 8), (16, 16)), q=8, k=16, p=10, seed=20250109):
     return out
 
 
+def rank_section(S, tol=1e-8, k_probe=48, p=10):
+    """Tolerance-driven rank on the bench geometry and operator: one tagged sketch at
+    r = k_probe + p picks the uniform k for ``tol``; a plan at that k then compresses,
+    and the exact relative Frobenius error is reported."""
+    import torch
+    P, g, op, wl = S["P"], S["g"], S["op"], S["wl"]
+    ell = P.tag_columns(g.box_ptr, g.lattice, wl.extra_tag_cols)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    probe = P.Plan(g.box_ptr, g.lattice, k_probe, T, p=p, extra_tag_cols=wl.extra_tag_cols)
+    G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(wl.seed, g.n, k_probe + p))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k, _ = P.tag_rank(probe, op, G, H, tol)
+    t_rank = time.perf_counter() - t0
+    plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=wl.extra_tag_cols)
+    G2, H2 = (P.colmajor(a) for a in W.gaussian_test_blocks(wl.seed, g.n, k + p))
+    h, rep = P.compress(plan, op, G2, H2, report=True)
+    err = h.error_fro(op)
+    log(f"rank for tol {tol:.0e}: k = {k} ({1e3 * t_rank:.1f} ms), compression {rep['ms_total']:.1f} ms, "
+        f"rel err {err:.2e}")
+    return {"tol": tol, "k_probe": k_probe, "k": k, "ms_rank": round(1e3 * t_rank, 3),
+            "ms_compress": round(rep["ms_total"], 3), "rel_err_fro": err}
+
+
 def cpu_baseline(S, nsample_boxes=4):
     """The oracle, as it stands, on a bounded sample: every stage of reconstruct_tag
     restricted to `nsample_boxes` row boxes (sketch rows, their post-processing and
@@ -445,6 +469,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-paper-geometry", action="store_true",
                     help="skip the random-point geometry measurement")
+    ap.add_argument("--no-rank", action="store_true",
+                    help="skip the tolerance-driven rank measurement")
     ap.add_argument("--no-bn", action="store_true",
                     help="skip the block-nullification (Alg. 1) comparison")
     ap.add_argument("--no-basic", action="store_true",
@@ -536,6 +562,12 @@ def main():
             out["paper_geometry"] = paper_geometry_section()
         except Exception as e:  # extra measurement: never lose the line
             out["paper_geometry"] = {"error": repr(e)}
+    if not args.no_rank:
+        try:
+            log("tolerance-driven rank")
+            out["rank_choice"] = [rank_section(S, tol) for tol in (1e-8, 1e-9)]
+        except Exception as e:  # extra measurement: never lose the line
+            out["rank_choice"] = {"error": repr(e)}
     if not args.no_bn:
         try:
             log("Alg. 1 comparison (block nullification)")
