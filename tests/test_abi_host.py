@@ -192,3 +192,29 @@ def test_explicit_list_errors():
         with pytest.raises(BlrError) as e:
             Plan(g.box_ptr, None, 2, Tc, p=1, extra_tag_cols=3, near=lists)
         assert e.value.name == name, (name, e.value)
+
+
+def test_comparison_and_rank_entry_points_validate_on_the_host():
+    """Alg. 1 / Alg. 3 / rank entry points: the block-nullification width equals the
+    oracle's, and NULL outputs or operators are refused before any device work."""
+    import ctypes
+    from paper_2501_05528_amd.api import Plan
+    L = _lib()
+    g = W.grid_geometry(2, (5, 4), (3, 4))
+    near = O.near_lists(g.lattice)
+    T = W.tag_matrix(7, g.nboxes, O.num_tag_columns(near, 3))
+    pl = Plan(g.box_ptr, g.lattice, 2, T, p=1, extra_tag_cols=3)
+    s = ctypes.c_int64()
+    assert L.blr_bn_min_columns(pl._h, ctypes.byref(s)) == 0
+    assert s.value == O.bn_columns(g.box_ptr, near, 3) == 3 + 9 * 12
+    assert L.blr_bn_min_columns(pl._h, None) == 1
+    out = ctypes.c_void_p()
+    k = ctypes.c_int32()
+    dummy = ctypes.c_void_p(8)                # never dereferenced: the operator check fails first
+    assert L.blr_basic_compress(pl._h, None, dummy, dummy, 0, None, ctypes.byref(out), None) == 1
+    assert b"operator" in L.blr_last_error_message()
+    assert L.blr_basic_compress(pl._h, None, dummy, dummy, 0, None, None, None) == 1
+    assert L.blr_bn_compress(pl._h, None, s.value, dummy, dummy, 0, None, ctypes.byref(out), None) == 1
+    assert out.value is None
+    assert L.blr_tag_rank(pl._h, None, dummy, dummy, 1e-8, None, ctypes.byref(k), None) == 1
+    assert L.blr_tag_rank(pl._h, None, dummy, dummy, 1e-8, None, None, None) == 1
