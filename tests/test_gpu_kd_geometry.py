@@ -5,7 +5,8 @@ whose cells share a boundary (caller neighbour lists, greedy probe colours, no l
 * Tagging (Alg. 2 + Table 1) with the built-in kernel operator: sketches to 1e-12 of their
   largest entry, every reconstructed block to 1e-11 max|A|, relative Frobenius error in the
   1.5 band of the oracle's, and the product count 2 ell r + b k + (colours) m_max.
-* Alg. 3 on the same geometry and operator: per-box samples to 1e-12, blocks to 1e-11.
+* Alg. 3 on the same geometry and operator: per-box samples to 1e-12, blocks to 1e-11; Alg. 1
+  on the 2D case (uneven neighbourhoods): projected samples and blocks to 1e-11.
 """
 import numpy as np
 import pytest
@@ -106,4 +107,32 @@ def test_basic_vs_oracle(run):
         got = hb.part(name).cpu().numpy()
         assert np.max(np.abs(got - bres[name])) <= 1e-12 * np.max(np.abs(bres[name])), name
     worst = _worst_block(run, hb, bres)
+    assert worst <= 1e-11, worst
+
+
+def test_bn_on_kd_geometry_2d():
+    """Alg. 1 on the 2D random-point geometry: uneven neighbourhoods give s = r + the rows
+    of the largest one; projected samples to 1e-11, blocks to 1e-11 max|A|."""
+    import torch
+    import paper_2501_05528_amd as P
+    n, dim, levels, kind, k, p, seed = CASES["log2d_n8100"]
+    g, near, _ = W.kd_geometry(n, dim, levels, seed)
+    ell = O.num_tag_columns(near, 3)
+    T = W.tag_matrix(seed, g.nboxes, ell)
+    s = O.bn_columns(g.box_ptr, near, k + p)
+    Om, Ps = W.gaussian_test_blocks(seed + 1, g.n, s)
+    A = O.KernelOperator(kind, g.pts).block()
+    res = O.reconstruct_bn(O.DenseOperator(A), g.box_ptr, None, k, p, Om, Ps, near=near)
+    _announce(f"bn on kd geometry: N={g.n} b={g.nboxes} s={s}")
+    plan = P.Plan(g.box_ptr, None, k, T, p=p, extra_tag_cols=3, near=near)
+    assert P.bn_min_columns(plan) == s
+    op = P.Operator.kernel(kind, g.pts)
+    h, rep = P.bn_compress(plan, op, P.colmajor(Om), P.colmajor(Ps), keep_samples=True)
+    torch.cuda.synchronize()
+    assert rep["applies_At"] == s
+    for name in ("SY", "SZ"):
+        got = h.part(name).cpu().numpy()
+        assert np.max(np.abs(got - res[name])) <= 1e-11 * np.max(np.abs(res[name])), name
+    run = dict(g=g, k=k, plan=plan, A=A)
+    worst = _worst_block(run, h, res)
     assert worst <= 1e-11, worst

@@ -29,23 +29,38 @@ def _case(name):
     raise KeyError(name)
 
 
-@pytest.fixture(scope="module", params=["planted", "log_ragged"])
+class Matmat:
+    def __init__(self, A):
+        self.A = A
+        self.At = A.t().contiguous()
+
+    def __call__(self, X, trans):
+        return (self.At if trans else self.A) @ X
+
+
+@pytest.fixture(scope="module", params=["planted", "log_ragged", "planted_callback"])
 def run(request):
     import paper_2501_05528_amd as P
-    g, A, k, p, seed = _case(request.param)
+    name = request.param
+    g, A, k, p, seed = _case(name.replace("_callback", ""))
     near = O.near_lists(g.lattice)
     T = W.tag_matrix(seed, g.nboxes, O.num_tag_columns(near, 3))
     G, H = W.gaussian_test_blocks(seed, g.n, k + p)
     res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, k, p, 3, T, G, H, steps=("I",))
     sy = O.box_singular_values(res["Yhat"], g.box_ptr)
     sz = O.box_singular_values(res["Zhat"], g.box_ptr)
-    _announce(f"rank {request.param} N={g.n} b={g.nboxes} r={k + p}")
+    _announce(f"rank {name} N={g.n} b={g.nboxes} r={k + p}")
     plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
-    op = P.Operator.kernel("log", g.pts) if request.param == "log_ragged" else P.Operator.dense(P.colmajor(A))
+    if name == "log_ragged":
+        op = P.Operator.kernel("log", g.pts)
+    elif name == "planted_callback":
+        op = P.Operator.from_matmat(g.n, Matmat(P.colmajor(A)))
+    else:
+        op = P.Operator.dense(P.colmajor(A))
     Gd, Hd = P.colmajor(G), P.colmajor(H)
     got = {tol: P.tag_rank(plan, op, Gd, Hd, tol) for tol in TOLS}
     return dict(P=P, g=g, A=A, k=k, sy=sy, sz=sz, got=got, plan=plan, op=op, Gd=Gd, Hd=Hd,
-                name=request.param)
+                name=name)
 
 
 def test_singular_values_vs_oracle(run):
@@ -63,7 +78,7 @@ def test_rank_vs_oracle(run):
         near = any(np.any(np.abs(s - tol * s[:, 0].max()) <= 1e-8 * tol * s[:, 0].max()) for s in (sy, sz))
         if not near:
             assert k_gpu == k_or
-    if run["name"] == "planted":
+    if run["name"].startswith("planted"):
         assert all(run["got"][tol][0] == run["k"] for tol in TOLS[1:])
 
 
