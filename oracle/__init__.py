@@ -21,8 +21,9 @@ refine          mixed-precision tagging with one FP64 refinement sketch (not in 
 basic           Alg. 3 (basic randomized SVD per box), the paper's benchmark for step (I)
 bn              Alg. 1 (block nullification), the method tagging improves on
 rank            tolerance-driven choice of the uniform rank from the tagged samples
+truncate        per-box ranks from a tolerance by truncating a computed representation
 """
-from . import admissibility, operators, tagging, reconstruct, refine, basic, bn, rank  # noqa: F401
+from . import admissibility, operators, tagging, reconstruct, refine, basic, bn, rank, truncate  # noqa: F401
 from .admissibility import near_lists, far_lists, colours, greedy_colours, lists_and_colours, num_tag_columns  # noqa: F401
 from .operators import DenseOperator, KernelOperator, CountingOperator  # noqa: F401
 from .tagging import (extended_test_matrix, null_space, projected_tags, aspect_ratio,  # noqa: F401
@@ -34,3 +35,4 @@ from .refine import (sample_basis, sample_bases, mixed_test_blocks, far_sample, 
 from .basic import masked_test_matrix, basic_bases, reconstruct_basic  # noqa: F401
 from .bn import bn_columns, neighbour_rows, null_r, bn_bases, reconstruct_bn  # noqa: F401
 from .rank import box_singular_values, rank_for_tolerance  # noqa: F401
+from .truncate import representation_norm, truncate_ublr  # noqa: F401

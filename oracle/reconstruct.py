@@ -31,14 +31,6 @@ def cores(op, U: np.ndarray, V: np.ndarray, box_ptr: np.ndarray, k: int) -> np.n
     return Ubd.T @ W
 
 
-def cores_pair(op, U: np.ndarray, V: np.ndarray, box_ptr, i: int, j: int) -> np.ndarray:
-    """One block Atil_ij = U_i* A_ij V_j (eq. uniformBLRblock), evaluated with entry
-    access; used to sample large problems where the full product is too slow."""
-    ri = np.arange(int(box_ptr[i]), int(box_ptr[i + 1]))
-    cj = np.arange(int(box_ptr[j]), int(box_ptr[j + 1]))
-    return U[ri].T @ op.block(ri, cj) @ V[cj]
-
-
 def nearfield_probes(op, U, V, Atil, box_ptr, near, colour, k: int):
     """B from 3^d sparse identity probes (Table 1 step 3; eq. sparse_struct_ids).
 

@@ -247,6 +247,78 @@ def test_p6_apply_equals_matrix_for_exact_rank(planted):
     assert np.allclose(yt, A.T @ x, atol=1e-11 * np.abs(A.T @ x).max())
 
 
+def _random_factors(g, k, seed):
+    """Unstructured U, V, Atil and near blocks B on the lattice neighbour pairs."""
+    rng = np.random.default_rng(seed)
+    near = O.near_lists(g.lattice)
+    bp = g.box_ptr
+    U = rng.standard_normal((g.n, k))
+    V = rng.standard_normal((g.n, k))
+    At = rng.standard_normal((g.nboxes * k, g.nboxes * k))
+    B = {(i, j): rng.standard_normal((bp[i + 1] - bp[i], bp[j + 1] - bp[j]))
+         for i in range(g.nboxes) for j in near[i]}
+    return U, V, At, B
+
+
+def test_dense_reconstruction_entries_bruteforce():
+    """Entry (p, q) of U Atil V* + B (eq. uniformBLRfull) is
+    sum_a sum_c U[p, a] Atil[i k + a, j k + c] V[q, c], plus B_ij[p - start_i, q - start_j]
+    when j is a neighbour of i; evaluated with scalar loops on a ragged grid."""
+    g = W.grid_geometry(2, (4, 3), (3, 2), jitter=0.2, seed=5)
+    k = 2
+    U, V, At, B = _random_factors(g, k, 17)
+    Ah = O.dense_reconstruction(U, V, At, B, g.box_ptr, k)
+    bp = g.box_ptr
+    box_of = np.repeat(np.arange(g.nboxes), np.diff(bp))
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        p, q = (int(v) for v in rng.integers(0, g.n, 2))
+        i, j = int(box_of[p]), int(box_of[q])
+        ref = 0.0
+        for a in range(k):
+            for c in range(k):
+                ref += U[p, a] * At[i * k + a, j * k + c] * V[q, c]
+        if (i, j) in B:
+            ref += B[(i, j)][p - bp[i], q - bp[j]]
+        assert abs(Ah[p, q] - ref) <= 1e-13 * (1 + abs(ref)), (p, q)
+
+
+def test_dense_reconstruction_planted_factors(planted):
+    """With the planted matrix's own bases (U*_i, V*_j), Atil = U* A V and
+    B_ij = A_ij - U*_i Atil_ij V*_j^T on neighbour pairs, the reconstruction is A itself."""
+    g, A, k = planted["g"], planted["A"], planted["wl"].k
+    bp = g.box_ptr
+    U = np.vstack(planted["us"])
+    V = np.vstack(planted["vs"])
+    Ubd = scipy.linalg.block_diag(*planted["us"])
+    Vbd = scipy.linalg.block_diag(*planted["vs"])
+    At = Ubd.T @ A @ Vbd
+    near = O.near_lists(g.lattice)
+    B = {}
+    for i in range(g.nboxes):
+        for j in near[i]:
+            ri, cj = slice(bp[i], bp[i + 1]), slice(bp[j], bp[j + 1])
+            B[(i, j)] = A[ri, cj] - planted["us"][i] @ At[i * k:(i + 1) * k, j * k:(j + 1) * k] @ planted["vs"][j].T
+    Ah = O.dense_reconstruction(U, V, At, B, bp, k)
+    assert np.max(np.abs(Ah - A)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_dense_reconstruction_agrees_with_apply_and_fro():
+    """The dense form, the apply (both orientations) and the block-wise Frobenius error
+    are three separate evaluations of one representation: they must agree."""
+    g = W.grid_geometry(2, 4, 3, jitter=0.1, seed=2)
+    k = 3
+    U, V, At, B = _random_factors(g, k, 23)
+    Ah = O.dense_reconstruction(U, V, At, B, g.box_ptr, k)
+    x = np.random.default_rng(4).standard_normal((g.n, 2))
+    for trans, M in ((False, Ah), (True, Ah.T)):
+        y = O.ublr_apply(U, V, At, B, g.box_ptr, k, x, trans=trans)
+        assert np.max(np.abs(y - M @ x)) <= 1e-12 * np.max(np.abs(M @ x))
+    A = O.KernelOperator("log", g.pts).block()
+    fro = O.rel_fro_error(O.DenseOperator(A), U, V, At, B, g.box_ptr, k)
+    assert np.isclose(fro, np.linalg.norm(A - Ah) / np.linalg.norm(A), rtol=1e-12)
+
+
 # ---------------------------------------------------------------- P7 matvec counts
 def test_p7_matvec_counts(planted):
     """Sketch 2 ell r products (Section 4.2), cores bk and near field 3^d m (Table 1)."""

@@ -165,6 +165,36 @@ def planted_exact_rank(geom: Geometry, k: int, seed: int):
     return A, ustar, vstar
 
 
+def planted_ragged_rank(geom: Geometry, ranks_u, ranks_v, seed: int):
+    """Dense N x N matrix with planted uniform-BLR structure of per-box ranks.
+
+    As ``planted_exact_rank`` but far block (i, j) is ``Ustar_i @ S_ij @ Vstar_j.T`` with
+    ``Ustar_i`` m_i x ranks_u[i] and ``Vstar_j`` m_j x ranks_v[j] orthonormal and S_ij
+    N(0,1), so box row i has far-field rank ranks_u[i] and box column j rank ranks_v[j].
+    Returns (A column-major, Ustar list, Vstar list).
+    """
+    g = rng(seed, STREAM_SYNTH_A)
+    b = geom.nboxes
+    bp = geom.box_ptr
+    ustar, vstar = [], []
+    for i in range(b):
+        mi = int(bp[i + 1] - bp[i])
+        for lst, kk in ((ustar, int(ranks_u[i])), (vstar, int(ranks_v[i]))):
+            q, rr = np.linalg.qr(g.standard_normal((mi, kk)))
+            lst.append(q * np.sign(np.diag(rr))[None, :])
+    A = np.zeros((geom.n, geom.n), order="F")
+    lat = geom.lattice.astype(np.int64)
+    for i in range(b):
+        for j in range(b):
+            ri = slice(bp[i], bp[i + 1])
+            cj = slice(bp[j], bp[j + 1])
+            if np.max(np.abs(lat[i] - lat[j])) <= 1:
+                A[ri, cj] = g.standard_normal((bp[i + 1] - bp[i], bp[j + 1] - bp[j]))
+            else:
+                A[ri, cj] = ustar[i] @ g.standard_normal((ustar[i].shape[1], vstar[j].shape[1])) @ vstar[j].T
+    return A, ustar, vstar
+
+
 def blocks_for_rank(n: int, k: int, dim: int) -> int:
     """Block count that balances storage and matvecs for flat uBLR (Section 7 sizing rule)."""
     return int(math.floor(math.sqrt((3 ** dim) * n / k)))
