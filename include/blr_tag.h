@@ -470,6 +470,22 @@ blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const doub
                      double* y, int64_t ldy, void* stream);
 
 /*
+ * blr_apply without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and kernels as blr_apply; the
+ * workspace lives in a fixed 32 MiB array (4194304 doubles) that the library
+ * holds on every device it runs on until the process ends.  A call whose
+ * workspace ((2 + s) b k ncols doubles) exceeds that returns
+ * BLR_ERR_INVALID_ARG naming the limit (split the columns over several calls).
+ * All calls on one device share the array: calls that overlap in time on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller; calls queued on one stream are ordered.  Nothing in the array needs
+ * to start at zero (every word a call reads, the same call writes first).
+ */
+blr_status blr_apply_noalloc(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x,
+                             int64_t ldx, double* y, int64_t ldy, void* stream);
+
+/*
  * Exact relative Frobenius error ||A - A_uBLR||_F / ||A||_F of a built-in
  * operator, block by block with entry access (evaluation harness; not part
  * of the black-box method).  Synchronises the stream.

@@ -131,6 +131,8 @@ SIGNATURES = {
     "blr_server_destroy": (None, [c_void_p]),
     "blr_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p]),
+    "blr_apply_noalloc": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                    c_void_p]),
     "blr_error_fro": (c_int32, [c_void_p, c_void_p, c_void_p, P_f64]),
     "blr_error_power": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, P_f64, P_f64]),
 }

@@ -273,10 +273,12 @@ class UBLR:
         check(lib().blr_ublr_export(self._h, PARTS[name], out.ctypes.data_as(c_void_p), cnt, _stream(stream)))
         return out
 
-    def apply(self, x, trans: bool = False, stream=None):
-        y = colmajor_empty(self.plan.n, x.shape[1], x.device)
-        check(lib().blr_apply(self._h, 1 if trans else 0, x.shape[1], _ptr(x), _ld(x), _ptr(y),
-                              _ld(y), _stream(stream)))
+    def apply(self, x, trans: bool = False, stream=None, out=None, noalloc: bool = False):
+        """y = A_uBLR x (or A_uBLR* x).  ``out``: optional column-major N x ncols result
+        buffer; ``noalloc``: use blr_apply_noalloc (library-held workspace, no allocation)."""
+        y = colmajor_empty(self.plan.n, x.shape[1], x.device) if out is None else out
+        fn = lib().blr_apply_noalloc if noalloc else lib().blr_apply
+        check(fn(self._h, 1 if trans else 0, x.shape[1], _ptr(x), _ld(x), _ptr(y), _ld(y), _stream(stream)))
         return y
 
     def error_fro(self, op: Operator, stream=None) -> float:

@@ -15,6 +15,13 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 
+// Workspace of blr_apply_noalloc: one fixed array per device, resident until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the host
+// it names a stand-in, not device memory); it uses the per-device address that
+// noalloc_scratch() obtains with hipGetSymbolAddress.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 22;   // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace blr {
 
 namespace {
@@ -94,6 +101,24 @@ int current_device() {
     int d = -1;
     HIPC(hipGetDevice(&d));
     return d;
+}
+
+// Device address of `scratch` on device `dev` (the current device), looked up once per
+// device; every kernel argument and copy uses this address, never the array's name.
+double* noalloc_scratch(int dev) {
+    static std::mutex mu;
+    static std::map<int, double*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(BLR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    addr[dev] = static_cast<double*>(p);
+    return static_cast<double*>(p);
 }
 
 const blr::PlanData& plan_of(const blr_plan* p) {
@@ -237,6 +262,14 @@ void DeviceTables::release() {
     dfree(nearm);
     dfree(colour);
     dfree(pair_row);
+}
+
+const DeviceTables* PlanData::resident_tables() {
+    const int devid = current_device();
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& t : dev)
+        if (t->device == devid) return t.get();
+    return nullptr;
 }
 
 const DeviceTables& PlanData::tables() {
@@ -1153,6 +1186,35 @@ blr_status blr_apply(const blr_ublr* h, int32_t trans, int64_t ncols, const doub
         AsyncTemps tmp(s);
         double* work = tmp.get(apply_workspace_doubles(P, ncols));
         launch_ublr_apply(P, t, d.U, d.V, d.Atil, d.B, trans ? 1 : 0, ncols, x, ldx, y, ldy, work, s);
+    });
+}
+
+blr_status blr_apply_noalloc(const blr_ublr* h, int32_t trans, int64_t ncols, const double* x, int64_t ldx,
+                             double* y, int64_t ldy, void* stream) {
+    return guard([&] {
+        if (!h || !h->d) fail(BLR_ERR_INVALID_ARG, "NULL handle");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        if (ncols < 0) fail(BLR_ERR_INVALID_ARG, "negative ncols");
+        if (ncols == 0) return;
+        if (ncols > 65535) fail(BLR_ERR_INVALID_ARG, "at most 65535 columns per call");
+        if (!x || !y) fail(BLR_ERR_INVALID_ARG, "NULL x or y");
+        check_ld(ldx, P.n, "x");
+        check_ld(ldy, P.n, "y");
+        if (d.device != current_device()) fail(BLR_ERR_INVALID_ARG, "handle belongs to another device");
+        const int64_t need = apply_workspace_doubles(P, ncols);
+        if (need > kNoAllocScratchDoubles) {
+            std::ostringstream os;
+            os << "blr_apply_noalloc: the workspace of " << need << " doubles exceeds the fixed scratch of "
+               << kNoAllocScratchDoubles << " doubles (32 MiB); pass fewer columns per call or use blr_apply";
+            fail(BLR_ERR_INVALID_ARG, os.str());
+        }
+        // The handle was built on this device, so the plan's tables are resident here.
+        const DeviceTables* t = d.plan->resident_tables();
+        if (!t) fail(BLR_ERR_INVALID_ARG, "the plan's device tables are not resident on this device");
+        double* work = noalloc_scratch(d.device);
+        launch_ublr_apply(P, *t, d.U, d.V, d.Atil, d.B, trans ? 1 : 0, ncols, x, ldx, y, ldy, work,
+                          static_cast<hipStream_t>(stream));
     });
 }
 

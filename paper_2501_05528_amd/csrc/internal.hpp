@@ -66,6 +66,7 @@ struct PlanData {
     std::mutex mu;
     std::vector<std::unique_ptr<DeviceTables>> dev;
     const DeviceTables& tables();  // tables for the current device (uploads on first use)
+    const DeviceTables* resident_tables();  // tables for the current device if uploaded, else NULL
     ~PlanData();
 };
 
