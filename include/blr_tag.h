@@ -577,7 +577,10 @@ typedef struct blr_server blr_server;
 typedef struct blr_server_job_stats {
     double t_submit, t_start, t_end;   /* host monotonic clock, seconds */
     double ms_device;                  /* the job's compression on its stream (events) */
-    int64_t footprint;                 /* bytes charged against the budget */
+    double dev_start_ms, dev_end_ms;   /* the job's interval on its slot's stream (device
+                                          events, ms since the server was created; -1 if
+                                          the events failed) */
+    int64_t footprint;                 /* bytes charged against the budget while it runs */
     int32_t slot;                      /* slot that ran the job */
     int32_t status;                    /* blr_status of the job */
 } blr_server_job_stats;
@@ -585,7 +588,10 @@ typedef struct blr_server_job_stats {
 /*
  * Creates a server on the current device with `slots` concurrent jobs (1..16, each
  * with its own stream) and an HBM budget in bytes for the admitted jobs' footprints
- * (blr_plan_footprint).
+ * (blr_plan_footprint).  A running job is charged its whole footprint; once it
+ * completes, its result (U, V, Atil, B; the whole footprint with
+ * keep_intermediates) stays charged until blr_server_wait hands it over, so
+ * results that nobody claims hold budget and can stall admission.
  */
 blr_status blr_server_create(int64_t hbm_budget, int32_t slots, blr_server** out);
 

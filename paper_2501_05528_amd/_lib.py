@@ -65,7 +65,8 @@ class BatchReport(ctypes.Structure):
 
 class ServerJobStats(ctypes.Structure):
     _fields_ = [("t_submit", c_double), ("t_start", c_double), ("t_end", c_double),
-                ("ms_device", c_double), ("footprint", c_int64), ("slot", c_int32), ("status", c_int32)]
+                ("ms_device", c_double), ("dev_start_ms", c_double), ("dev_end_ms", c_double),
+                ("footprint", c_int64), ("slot", c_int32), ("status", c_int32)]
 
 
 BATCH_GRAPH = 1

@@ -70,6 +70,12 @@ struct PlanData {
     ~PlanData();
 };
 
+// Bytes of a compressed handle's outputs U, V (N x k each), Atil (bk x bk) and B.
+inline int64_t result_bytes(const PlanData& P) {
+    const int64_t bk = static_cast<int64_t>(P.b) * P.k;
+    return static_cast<int64_t>(sizeof(double)) * (2 * P.n * P.k + bk * bk + P.b_values);
+}
+
 // Host planner (plan.cpp).
 std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params* prm);
 int tag_columns(const blr_geometry* g, int extra);

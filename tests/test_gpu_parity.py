@@ -199,6 +199,60 @@ def test_apply_parity(run):
             _close(y, yo, 1e-10)
 
 
+def _gpu_factors(run):
+    out = run["out"]
+    return out["U"], out["V"], out["Atil"], _blocks_B(run, out["B"][:, 0])
+
+
+def test_apply_identical_factors(run):
+    """blr_apply against the oracle's apply of the library's own U, Atil, V and B: the same
+    sums in a different order, so agreement to 1e-12 of the largest output entry."""
+    g, k = run["c"]["g"], run["c"]["k"]
+    P = run["P"]
+    U, V, At, B = _gpu_factors(run)
+    for ncols in (1, 3, 21):
+        x = np.random.default_rng(5 + ncols).standard_normal((g.n, ncols))
+        xd = P.colmajor(x)
+        for trans in (False, True):
+            y = _np(run["h"].apply(xd, trans=trans))
+            yo = O.ublr_apply(U, V, At, B, g.box_ptr, k, x, trans=trans)
+            _close(y, yo, 1e-12)
+
+
+def test_error_fro_identical_factors(run):
+    """blr_error_fro against the oracle's exact relative Frobenius error of the *same* factors.
+
+    Both evaluate sqrt(sum ||A_ij - U_i Atil_ij V_j* - B_ij||_F^2 / sum ||A_ij||_F^2); each
+    entry of the error matrix carries a rounding error of a few units of 2^-53 times the
+    entries it is formed from, so the two may differ by about 1e-15 in absolute terms
+    (relative to ||A||_F) on top of 1e-10 relative.  Bound: 1e-10 e + 2e-14."""
+    g, k = run["c"]["g"], run["c"]["k"]
+    U, V, At, B = _gpu_factors(run)
+    e_gpu = run["h"].error_fro(run["op"])
+    e_or = O.rel_fro_error(O.DenseOperator(run["A"]), U, V, At, B, g.box_ptr, k)
+    _announce(f"{run['c']['name']}: blr_error_fro {e_gpu:.6e}, oracle on the same factors {e_or:.6e}")
+    assert abs(e_gpu - e_or) <= 1e-10 * e_or + 2e-14
+
+
+def test_power_estimate_identical_factors(run):
+    """blr_error_power against the oracle's 20-step power estimate on the same factors and
+    the same start vector.  The library forms E x as A x - A_uBLR x, the oracle as
+    (A - A_uBLR) x: the rounding of that difference is about sqrt(N) 2^-53 ||A||_2 per
+    product, and 20 steps carry it into the estimate, hence 1e-10 relative plus
+    1e-12 ||A||_2; ||A||_2 itself to 1e-10 relative."""
+    g, k = run["c"]["g"], run["c"]["k"]
+    P = run["P"]
+    U, V, At, B = _gpu_factors(run)
+    x0 = W.gaussian_colmajor(run["c"]["seed"], W.STREAM_POWER, g.n, 1)[:, 0]
+    e_gpu, a_gpu = run["h"].error_power(run["op"], P.colmajor(x0), iters=20)
+    A = run["A"]
+    E = A - O.dense_reconstruction(U, V, At, B, g.box_ptr, k)
+    e_or = O.power_norm_estimate(lambda v: E @ v, lambda v: E.T @ v, g.n, x0, 20)
+    a_or = O.power_norm_estimate(lambda v: A @ v, lambda v: A.T @ v, g.n, x0, 20)
+    assert abs(a_gpu - a_or) <= 1e-10 * a_or
+    assert abs(e_gpu - e_or) <= 1e-10 * e_or + 1e-12 * a_or, (e_gpu, e_or)
+
+
 def test_operator_apply_parity(run):
     P = run["P"]
     g = run["c"]["g"]

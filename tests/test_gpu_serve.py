@@ -2,8 +2,14 @@
 budget, jobs running concurrently on the slots' streams.
 
 * Every job's U, V, Atil, B in a concurrent mix equal its solo blr_tag_compress run bit
-  for bit (a job's arithmetic never depends on the other jobs).
+  for bit (a job's arithmetic never depends on the other jobs), and the device intervals
+  of the jobs (events on the slots' streams) overlap.
+* One served job of each kernel class has a relative Frobenius error in the oracle's band:
+  FP64 within [1/1.5, 1.5] of the oracle's plain-tagging error (or 1e-12 apart), mixed
+  precision at most 1.5 times it (plus 1e-12).
 * With a budget that fits only one of two jobs, their device intervals never overlap.
+* A completed result stays charged until it is claimed: with a budget of one job's
+  footprint, a second job waits until the first job's result is handed over.
 * A job larger than the whole budget is refused with BLR_ERR_BUSY.
 * Poisson arrivals (seeded) all complete; latency percentiles are reported.
 """
@@ -28,7 +34,7 @@ def jobs():
     import paper_2501_05528_amd as P
     out = []
     precs = ["bf16", "fp64", "fp32"]
-    for q, wl in enumerate(W.uneven_batch_jobs(6, 20250105, n_lo=2048, n_hi=8192)):
+    for q, wl in enumerate(W.uneven_batch_jobs(7, 20250105, n_lo=2048, n_hi=8192)):
         g = wl.geometry()
         near = O.near_lists(g.lattice)
         T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, 3))
@@ -37,7 +43,7 @@ def jobs():
         plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=3)
         out.append(dict(plan=plan, op=P.Operator.kernel(wl.kind, g.pts), G=P.colmajor(G), H=P.colmajor(H),
                         gamma_u=torch.as_tensor(gu, device="cuda"), gamma_v=torch.as_tensor(gv, device="cuda"),
-                        precision=precs[q % 3], n=g.n, kind=wl.kind, k=wl.k))
+                        precision=precs[q % 3], n=g.n, kind=wl.kind, k=wl.k, wl=wl))
         _announce(f"serve job {q}: N={g.n} k={wl.k} {wl.kind} {precs[q % 3]}")
     return out
 
@@ -69,10 +75,67 @@ def test_alone_equals_mix(jobs):
         got = _parts(h)
         for x in ("U", "V", "Atil", "B"):
             assert (got[x] == solo[q][x]).all().item(), (q, x)
+        assert 0 <= st["dev_start_ms"] <= st["dev_end_ms"]
         for q2, (_, st2) in enumerate(results):
-            if q2 != q and st["t_start"] < st2["t_end"] and st2["t_start"] < st["t_end"]:
+            if q2 != q and st["dev_start_ms"] < st2["dev_end_ms"] and st2["dev_start_ms"] < st["dev_end_ms"]:
                 overlap += 1
-    _announce(f"mix of {len(jobs)} jobs on 4 slots: {overlap // 2} overlapping pairs")
+    span = max(st["dev_end_ms"] for _, st in results) - min(st["dev_start_ms"] for _, st in results)
+    busy = sum(st["dev_end_ms"] - st["dev_start_ms"] for _, st in results)
+    _announce(f"mix of {len(jobs)} jobs on 4 slots: {overlap // 2} pairs overlap on the device; "
+              f"sum of device intervals {busy:.1f} ms over a span of {span:.1f} ms")
+    assert overlap > 0
+    for j, (h, _) in zip(jobs, results):
+        j["served"] = h
+
+
+def test_served_jobs_in_oracle_band(jobs):
+    """One served job per kernel class against the FP64 oracle's plain-tagging error on the
+    same inputs (the mixed modes are allowed to be more accurate: one-sided band)."""
+    seen = set()
+    for q, j in enumerate(jobs):
+        if j["kind"] in seen or "served" not in j:
+            continue
+        seen.add(j["kind"])
+        wl = j["wl"]
+        g = wl.geometry()
+        A = O.KernelOperator(wl.kind, g.pts).block()
+        near = O.near_lists(g.lattice)
+        T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, 3))
+        G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+        res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, wl.k, wl.p, 3, T, G, H)
+        e_or = O.rel_fro_error(O.DenseOperator(A), res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, wl.k)
+        e_srv = j["served"].error_fro(j["op"])
+        _announce(f"served job {q} ({j['kind']}, {j['precision']}, N={g.n}): error {e_srv:.3e}, oracle {e_or:.3e}")
+        if j["precision"] == "fp64":
+            assert abs(e_srv - e_or) <= 1e-12 or 1 / 1.5 <= e_srv / e_or <= 1.5
+        else:
+            assert e_srv <= 1.5 * e_or + 1e-12
+    assert len(seen) == len({j["kind"] for j in jobs})
+
+
+def test_unclaimed_result_stays_charged(jobs):
+    """Budget = one job's footprint; the same job submitted twice.  While the first result
+    is unclaimed its output bytes stay charged, so the second job cannot be admitted
+    until blr_server_wait hands the first result over."""
+    import paper_2501_05528_amd as P
+    j = jobs[1]
+    f = P.footprint(j["plan"], j["precision"], j["G"].shape[1] if j["precision"] != "fp64" else 0)
+    srv = P.Server(hbm_budget=f, slots=2)
+    ta = srv.submit(j["plan"], j["op"], j["G"], j["H"], **_kw(j))
+    tb = srv.submit(j["plan"], j["op"], j["G"], j["H"], **_kw(j))
+    t_limit = time.monotonic() + 60.0
+    while not srv.done(ta):
+        assert time.monotonic() < t_limit, "first job did not finish"
+        time.sleep(0.002)
+    time.sleep(0.3)
+    assert not srv.done(tb)
+    t_claim = time.monotonic()
+    _, sa = srv.wait(ta)
+    _, sb = srv.wait(tb)
+    srv.close()
+    assert sa["status"] == 0 and sb["status"] == 0
+    assert sb["t_start"] >= t_claim, (sb["t_start"], t_claim)
+    _announce(f"second job admitted {1e3 * (sb['t_start'] - t_claim):.2f} ms after the first result was claimed")
 
 
 def test_budget_serialises(jobs):
