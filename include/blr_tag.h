@@ -410,15 +410,18 @@ blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t
                            blr_report* rep);
 
 /*
- * Tolerance-driven choice of the uniform rank (Section 2.3: the range finder
- * can pick its rank from a tolerance; Section 6: larger ranks can be chosen and
- * truncated as needed).  One tagged sketch and post-processing at the plan's
- * r = k + p columns (Alg. 2), then the singular values of every box's m_i x r
- * samples Yhat_i and Zhat_i.  *k_out = the largest over boxes and sides of
- * #{j : sigma_j(box) > tol * the largest singular value of that side over all
- * boxes}: the smallest uniform rank that keeps every such direction.  *k_out
- * = r means the tolerance was not reached within the sample (plan again with
- * a larger k); a plan with rank *k_out then compresses at that accuracy.
+ * A uniform rank from a singular-value threshold on the tagged samples (Section
+ * 2.3: the range finder can pick its rank from a tolerance).  One tagged sketch
+ * and post-processing at the plan's r = k + p columns (Alg. 2), then the
+ * singular values of every box's m_i x r samples Yhat_i and Zhat_i.  *k_out =
+ * the largest over boxes and sides of #{j : sigma_j(box) > tol * the largest
+ * singular value of that side over all boxes}: the smallest uniform rank that
+ * keeps every sample direction above the threshold.  *k_out = r means the
+ * threshold was not reached within the sample (plan again with a larger k).
+ * This is a per-direction threshold, not an error bound: the relative Frobenius
+ * error summed over all b^2 blocks at rank *k_out can exceed tol (about 5 tol
+ * on the 2D Laplace workload).  For a guaranteed tolerance compress at a larger
+ * k and call blr_ublr_truncate.
  * G, H as for blr_tag_compress.  sigma: optional host array 2 x b x r
  * (Y side then Z side, each box's values descending).  Synchronises the
  * stream; tol < 0 or NaN gives BLR_ERR_INVALID_ARG, non-finite samples
@@ -456,6 +459,36 @@ blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, 
  * copy on `stream` before returning.
  */
 blr_status blr_ublr_export(const blr_ublr* h, int32_t part, void* host, int64_t count, void* stream);
+
+/*
+ * Per-box ranks from a tolerance by truncating a compressed operator (Section 6:
+ * ranks can be chosen larger and truncated afterwards; Section 2.4: the range
+ * finder can work to a tolerance).  From h (any precision), a new handle *out
+ * whose far field is cut to the smallest per-box ranks that keep the change of
+ * the represented matrix within tol ||A_uBLR||_F:
+ *   rows: per box i the SVD of the far block row Atil(i, F_i); over all boxes
+ *   the smallest singular values are dropped while their squares sum to at
+ *   most half of (tol ||A_uBLR||_F)^2; U'_i = U_i W_i(:, 1:ku_i) and the block
+ *   row is rotated and cut likewise;
+ *   columns: the same on the far block columns of the row-truncated cores with
+ *   the rest of the budget (V'_j, kv_j);
+ *   near pairs: B'_ij = B_ij + U_i Atil_ij V_j* - U'_i Atil'_ij V'_j*, so every
+ *   near block is represented as before.
+ * The change of the far field is exactly the dropped squares (the two projections
+ * are orthogonal), so ||A_uBLR' - A_uBLR||_F <= tol ||A_uBLR||_F and the error
+ * against A grows by at most that much.  Layout stays uniform: U', V' are N x k
+ * with the columns beyond the box's rank zero, Atil' bk x bk with the matching
+ * rows and columns zero; apply, export and error calls work unchanged.
+ * ranks_u, ranks_v: optional host arrays of b; rel_change: optional,
+ * sqrt(dropped squares) / ||A_uBLR||_F.  h stays valid; *out is owned by the
+ * caller.  Synchronises the stream.  tol < 0 or not finite: BLR_ERR_INVALID_ARG;
+ * k > 64: BLR_ERR_UNSUPPORTED.
+ */
+blr_status blr_ublr_truncate(const blr_ublr* h, double tol, void* stream, blr_ublr** out, int32_t* ranks_u,
+                             int32_t* ranks_v, double* rel_change);
+
+/* Per-box ranks of a handle (host arrays of b): k everywhere unless truncated. */
+blr_status blr_ublr_ranks(const blr_ublr* h, int32_t* ranks_u, int32_t* ranks_v);
 
 /*
  * y = A_uBLR x = U (Atil (V* x)) + B x (trans = 0) or A_uBLR* x (trans = 1)

@@ -134,6 +134,8 @@ SIGNATURES = {
                             c_void_p]),
     "blr_apply_noalloc": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                     c_void_p]),
+    "blr_ublr_truncate": (c_int32, [c_void_p, c_double, c_void_p, POINTER(c_void_p), P_i32, P_i32, P_f64]),
+    "blr_ublr_ranks": (c_int32, [c_void_p, P_i32, P_i32]),
     "blr_error_fro": (c_int32, [c_void_p, c_void_p, c_void_p, P_f64]),
     "blr_error_power": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, P_f64, P_f64]),
 }

@@ -281,6 +281,26 @@ class UBLR:
         check(fn(self._h, 1 if trans else 0, x.shape[1], _ptr(x), _ld(x), _ptr(y), _ld(y), _stream(stream)))
         return y
 
+    def truncate(self, tol: float, stream=None):
+        """Per-box ranks from a tolerance (blr_ublr_truncate): (UBLR, ranks_u, ranks_v,
+        rel_change) with the ranks as numpy int32 arrays of b."""
+        b = self.plan.b
+        ku = np.zeros(b, dtype=np.int32)
+        kv = np.zeros(b, dtype=np.int32)
+        ch = c_double()
+        h = c_void_p()
+        check(lib().blr_ublr_truncate(self._h, float(tol), _stream(stream), byref(h),
+                                      ku.ctypes.data_as(_lib.P_i32), kv.ctypes.data_as(_lib.P_i32), byref(ch)))
+        return UBLR(h, self.plan, self.precision, self.r_lo), ku, kv, ch.value
+
+    def ranks(self):
+        """(ranks_u, ranks_v): per-box ranks (k everywhere unless truncated)."""
+        b = self.plan.b
+        ku = np.zeros(b, dtype=np.int32)
+        kv = np.zeros(b, dtype=np.int32)
+        check(lib().blr_ublr_ranks(self._h, ku.ctypes.data_as(_lib.P_i32), kv.ctypes.data_as(_lib.P_i32)))
+        return ku, kv
+
     def error_fro(self, op: Operator, stream=None) -> float:
         e = c_double()
         check(lib().blr_error_fro(self._h, op._h, _stream(stream), byref(e)))

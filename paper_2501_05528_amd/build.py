@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblrtag.so")
-SOURCES = ["plan.cpp", "bn.cpp", "kernels.hip", "kernels_lp.hip", "blackbox.hip", "api.hip", "server.cpp"]
+SOURCES = ["plan.cpp", "bn.cpp", "kernels.hip", "kernels_lp.hip", "blackbox.hip", "truncate.hip", "api.hip",
+           "server.cpp"]
 ARCH = "gfx950"
 
 

@@ -1122,6 +1122,120 @@ blr_status blr_tag_rank(const blr_plan* plan, const blr_operator* op, const doub
 
 void blr_ublr_destroy(blr_ublr* h) { delete h; }
 
+// Choose per-box ranks: drop the globally smallest singular values (b x k table, each box's
+// row descending) while the sum of their squares stays within `budget`.
+static std::vector<int32_t> drop_to_budget(const std::vector<double>& sig, int b, int k, double budget,
+                                           double* dropped) {
+    std::vector<std::tuple<double, int, int>> all;
+    all.reserve(static_cast<size_t>(b) * k);
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < k; ++j) {
+            const double v = sig[static_cast<size_t>(i) * k + j];
+            all.emplace_back(v * v, i, j);
+        }
+    std::sort(all.begin(), all.end());
+    std::vector<int32_t> ranks(b, k);
+    double acc = 0.0;
+    for (const auto& e : all) {
+        if (acc + std::get<0>(e) > budget) break;
+        acc += std::get<0>(e);
+        --ranks[std::get<1>(e)];
+    }
+    *dropped = acc;
+    return ranks;
+}
+
+blr_status blr_ublr_truncate(const blr_ublr* h, double tol, void* stream, blr_ublr** out, int32_t* ranks_u,
+                             int32_t* ranks_v, double* rel_change) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!h || !h->d || !out) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(BLR_ERR_INVALID_ARG, "tolerance must be a finite number >= 0");
+        const UblrData& d = *h->d;
+        const PlanData& P = *d.plan;
+        if (d.device != current_device()) fail(BLR_ERR_INVALID_ARG, "handle belongs to another device");
+        if (P.k > 64) fail(BLR_ERR_UNSUPPORTED, "truncation supports k <= 64");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const DeviceTables& t = d.plan->tables();
+        const int b = P.b, k = P.k;
+        const int64_t bk = static_cast<int64_t>(b) * k;
+        auto o = std::make_unique<UblrData>();
+        o->plan = d.plan;
+        o->device = d.device;
+        o->precision = d.precision;
+        o->r_lo = d.r_lo;
+        o->U = dalloc_sync(P.n * k);
+        o->V = dalloc_sync(P.n * k);
+        o->Atil = dalloc_sync(bk * bk);
+        o->B = dalloc_sync(P.b_values);
+        AsyncTemps tmp(s);
+        double* W = tmp.get(static_cast<int64_t>(b) * k * k);
+        double* Jm = tmp.get(static_cast<int64_t>(b) * k * k);
+        double* sig = tmp.get(static_cast<int64_t>(b) * k);
+        double* part = tmp.get(static_cast<int64_t>(b) * b + P.near_nnz);
+        int32_t* kdev = reinterpret_cast<int32_t*>(tmp.get(b));    // b ranks (int32) in b doubles
+        // ||A_uBLR||_F^2: far blocks ||Atil_ij||^2 (orthonormal bases), near blocks explicitly
+        launch_block_sq(P, d.Atil, part, s);
+        launch_near_repr_sq(P, t, d.U, d.V, d.Atil, d.B, part + static_cast<int64_t>(b) * b, s);
+        std::vector<double> hp(static_cast<size_t>(b) * b + P.near_nnz);
+        HIPC(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<uint8_t> nm(P.nearm);
+        HIPC(hipStreamSynchronize(s));
+        double norm2 = 0.0;
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j)
+                if (!nm[static_cast<size_t>(i) * b + j]) norm2 += hp[static_cast<size_t>(i) * b + j];
+        for (int64_t q = 0; q < P.near_nnz; ++q) norm2 += hp[static_cast<size_t>(b) * b + q];
+        if (!std::isfinite(norm2)) fail(BLR_ERR_NUMERICAL, "non-finite compressed operator");
+        const double budget = tol * tol * norm2;
+        std::vector<double> hs(static_cast<size_t>(b) * k);
+        auto fetch_sig = [&] {
+            HIPC(hipMemcpyAsync(hs.data(), sig, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            for (double v : hs)
+                if (!std::isfinite(v)) fail(BLR_ERR_NUMERICAL, "non-finite singular values in the truncation");
+        };
+        // rows: half of the budget
+        launch_trunc_svd(P, t, 0, d.Atil, W, sig, s);
+        fetch_sig();
+        double drop_u = 0.0, drop_v = 0.0;
+        std::vector<int32_t> ku = drop_to_budget(hs, b, k, 0.5 * budget, &drop_u);
+        HIPC(hipMemcpyAsync(kdev, ku.data(), b * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        launch_trunc_rows(P, d.Atil, o->Atil, W, kdev, s);
+        launch_trunc_basis(P, t, d.U, o->U, W, kdev, s);
+        // columns of the row-truncated cores: what the rows left of the budget
+        launch_trunc_svd(P, t, 1, o->Atil, Jm, sig, s);
+        fetch_sig();
+        std::vector<int32_t> kv = drop_to_budget(hs, b, k, budget - drop_u, &drop_v);
+        HIPC(hipMemcpyAsync(kdev, kv.data(), b * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        launch_trunc_cols(P, o->Atil, Jm, kdev, s);
+        launch_trunc_basis(P, t, d.V, o->V, Jm, kdev, s);
+        // near pairs keep their represented blocks
+        launch_trunc_near(P, t, d.U, d.V, d.Atil, o->Atil, W, Jm, d.B, o->B, s);
+        HIPC(hipStreamSynchronize(s));
+        o->ranks_u = ku;
+        o->ranks_v = kv;
+        if (ranks_u) std::memcpy(ranks_u, ku.data(), b * sizeof(int32_t));
+        if (ranks_v) std::memcpy(ranks_v, kv.data(), b * sizeof(int32_t));
+        if (rel_change) *rel_change = norm2 > 0.0 ? std::sqrt((drop_u + drop_v) / norm2) : 0.0;
+        auto H = std::make_unique<blr_ublr>();
+        H->d = std::move(o);
+        *out = H.release();
+    });
+}
+
+blr_status blr_ublr_ranks(const blr_ublr* h, int32_t* ranks_u, int32_t* ranks_v) {
+    return guard([&] {
+        if (!h || !h->d || !ranks_u || !ranks_v) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        const UblrData& d = *h->d;
+        const int b = d.plan->b;
+        for (int i = 0; i < b; ++i) {
+            ranks_u[i] = d.ranks_u.empty() ? d.plan->k : d.ranks_u[i];
+            ranks_v[i] = d.ranks_v.empty() ? d.plan->k : d.ranks_v[i];
+        }
+    });
+}
+
 blr_status blr_ublr_part_ptr(const blr_ublr* h, int32_t part, const void** ptr, int64_t* count) {
     if (ptr) *ptr = nullptr;
     return guard([&] {

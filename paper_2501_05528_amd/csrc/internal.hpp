@@ -122,6 +122,7 @@ struct UblrData {
     double* V0 = nullptr;
     double* SY = nullptr;         // mixed modes, keep_intermediates: refinement samples (N x r)
     double* SZ = nullptr;
+    std::vector<int32_t> ranks_u, ranks_v;  // per-box ranks after truncation (empty: all k)
     ~UblrData();
 };
 

@@ -123,6 +123,29 @@ void launch_err_fro(const OpData& op, const PlanData& P, const DeviceTables& t, 
                     const double* V, const double* Atil, const double* Bv, double* part,
                     hipStream_t s);
 
+// Truncation to per-box ranks (truncate.hip).  mode 0: far block rows of Atil, mode 1:
+// far block columns; W receives b k x k rotations (columns by descending singular value)
+// and sig b x k singular values.
+void launch_trunc_svd(const PlanData& P, const DeviceTables& t, int mode, const double* Atil, double* W,
+                      double* sig, hipStream_t s);
+// Aout = blockdiag(W_i(:, 1:ku_i))^T Ain (rows beyond ku_i zero)
+void launch_trunc_rows(const PlanData& P, const double* Ain, double* Aout, const double* W, const int32_t* ku,
+                       hipStream_t s);
+// A = A blockdiag(J_j(:, 1:kv_j)) in place (columns beyond kv_j zero)
+void launch_trunc_cols(const PlanData& P, double* A, const double* Jm, const int32_t* kv, hipStream_t s);
+// Sout(I_i, :) = S(I_i, :) W_i(:, 1:kr_i) (columns beyond kr_i zero)
+void launch_trunc_basis(const PlanData& P, const DeviceTables& t, const double* S, double* Sout, const double* W,
+                        const int32_t* kr, hipStream_t s);
+// part[i b + j] = ||Atil_ij||_F^2
+void launch_block_sq(const PlanData& P, const double* Atil, double* part, hipStream_t s);
+// part[q] = ||U_i Atil_ij V_j^T + B_ij||_F^2 for each neighbour pair q
+void launch_near_repr_sq(const PlanData& P, const DeviceTables& t, const double* U, const double* V,
+                         const double* Atil, const double* Bv, double* part, hipStream_t s);
+// Bout_ij = B_ij + U_i (Aold_ij - W_i Anew_ij J_j^T) V_j^T for each neighbour pair
+void launch_trunc_near(const PlanData& P, const DeviceTables& t, const double* U, const double* V,
+                       const double* Aold, const double* Anew, const double* W, const double* Jm,
+                       const double* Bin, double* Bout, hipStream_t s);
+
 // Deterministic dot product: part needs dot_parts() doubles; result in part[0].
 int dot_parts();
 void launch_dot(const double* x, const double* y, int64_t n, double* part, hipStream_t s);

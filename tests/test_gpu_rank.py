@@ -75,7 +75,10 @@ def test_rank_vs_oracle(run):
         k_gpu, _ = run["got"][tol]
         k_or = O.rank_for_tolerance(sy, sz, tol)
         _announce(f"{run['name']}: tol {tol:.0e} -> k {k_gpu} (oracle {k_or})")
-        near = any(np.any(np.abs(s - tol * s[:, 0].max()) <= 1e-8 * tol * s[:, 0].max()) for s in (sy, sz))
+        # the singular values themselves agree only to 1e-10 of the largest (test above), so a
+        # value that close to the threshold may fall on either side: excuse exactly those
+        near = any(np.any(np.abs(s - tol * s[:, 0].max()) <= max(1e-8 * tol, 2e-10) * s[:, 0].max())
+                   for s in (sy, sz))
         if not near:
             assert k_gpu == k_or
     if run["name"].startswith("planted"):
