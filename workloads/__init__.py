@@ -195,6 +195,18 @@ def planted_ragged_rank(geom: Geometry, ranks_u, ranks_v, seed: int):
     return A, ustar, vstar
 
 
+def slab_front(B: int, q: int):
+    """The frontal face of a thin slab (Section 7.2) as a compression geometry: the n x n face
+    points (n = B q, cell-centred in the unit square) in B x B boxes of q x q points, box-major
+    as ``grid_geometry``, and the plane index x + n y of every row (the permutation a slab
+    operator needs to map plan rows to grid points)."""
+    g = grid_geometry(2, B, q)
+    n = B * q
+    ix = np.floor(g.pts[:, 0] * n).astype(np.int64)
+    iy = np.floor(g.pts[:, 1] * n).astype(np.int64)
+    return g, ix + n * iy
+
+
 def blocks_for_rank(n: int, k: int, dim: int) -> int:
     """Block count that balances storage and matvecs for flat uBLR (Section 7 sizing rule)."""
     return int(math.floor(math.sqrt((3 ** dim) * n / k)))
