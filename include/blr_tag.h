@@ -196,6 +196,22 @@ typedef int32_t (*blr_apply_fn)(void* ctx, int32_t trans, int64_t ncols, const d
  * BLR_ERR_UNSUPPORTED for such operators.
  */
 blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_operator** out);
+
+/*
+ * The thin-slab Schur complement of Section 7.2 as a library-held black box
+ * (products only, like a callback operator).  Grid n x n x l (h = 1, zero
+ * Dirichlet values outside), 7-point finite differences of -Laplace - kappa^2
+ * (diagonal 6 - kappa_h^2, -1 per neighbour; the paper's 100 points per
+ * wavelength is kappa_h = 2 pi / 100), frontal face z = l - 1, internal planes
+ * eliminated: S = A_ff - A_fi A_ii^{-1} A_if, N = n^2, symmetric (A* = A).
+ * perm: host array of N, perm[row] = x + n y, the face point of operator row
+ * `row` (a permutation; copied).  Products use the separable exact solve: sine
+ * transforms in the plane and one tridiagonal z-line pivot per mode pair.
+ * Errors: n < 1, l < 1, bad perm, or an internal block that is not positive
+ * definite (a resonant slab) give BLR_ERR_INVALID_ARG.  Entry-based calls
+ * (blr_error_fro, mixed precision, batches) return BLR_ERR_UNSUPPORTED.
+ */
+blr_status blr_op_slab_create(int32_t n, int32_t l, double kappa_h, const int64_t* perm, blr_operator** out);
 void blr_op_destroy(blr_operator* op);
 
 /*

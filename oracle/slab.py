@@ -87,10 +87,13 @@ class SlabOperator:
         return self.matmat(X, rows)        # S is symmetric
 
     def block(self, rows=None, cols=None) -> np.ndarray:
-        """Entries S(rows, cols) in plan order (evaluation harness: S applied to unit vectors
-        of the requested columns)."""
+        """Entries S(rows, cols) in plan order (evaluation harness): S applied to unit vectors
+        of the requested columns, or, when fewer rows than columns are asked for, to those
+        of the rows (S is symmetric, so S(rows, cols) = S(cols, rows)^T)."""
+        r = np.arange(self.n) if rows is None else np.atleast_1d(np.asarray(rows))
         c = np.arange(self.n) if cols is None else np.atleast_1d(np.asarray(cols))
-        E = np.zeros((self.n, c.size))
-        E[c, np.arange(c.size)] = 1.0
-        Sc = self.matmat(E)
-        return Sc if rows is None else Sc[np.atleast_1d(np.asarray(rows))]
+        small, other, transpose = (r, c, True) if r.size < c.size else (c, r, False)
+        E = np.zeros((self.n, small.size))
+        E[small, np.arange(small.size)] = 1.0
+        Sx = self.matmat(E)[other]
+        return Sx.T if transpose else Sx

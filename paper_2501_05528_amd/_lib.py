@@ -90,6 +90,7 @@ SIGNATURES = {
     "blr_plan_tags": (c_int32, [c_void_p, P_f64, P_f64]),
     "blr_op_dense_create": (c_int32, [c_int64, c_void_p, c_int64, POINTER(c_void_p)]),
     "blr_op_kernel_create": (c_int32, [c_int32, c_int32, c_int64, P_f64, POINTER(c_void_p)]),
+    "blr_op_slab_create": (c_int32, [c_int32, c_int32, c_double, P_i64, POINTER(c_void_p)]),
     "blr_op_callback_create": (c_int32, [c_int64, APPLY_FN, c_void_p, POINTER(c_void_p)]),
     "blr_op_destroy": (None, [c_void_p]),
     "blr_op_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,

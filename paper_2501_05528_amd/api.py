@@ -191,6 +191,15 @@ class Operator:
         return cls(h, p.shape[0])
 
     @classmethod
+    def slab(cls, n: int, l: int, perm, kappa_h: float = 2.0 * np.pi / 100.0):
+        """Thin-slab Schur complement (blr_op_slab_create): n x n x l grid, frontal face
+        z = l - 1, perm[row] = plane index x + n y of operator row ``row``."""
+        pm = np.ascontiguousarray(perm, dtype=np.int64)
+        h = c_void_p()
+        check(lib().blr_op_slab_create(int(n), int(l), float(kappa_h), pm.ctypes.data_as(_lib.P_i64), byref(h)))
+        return cls(h, int(n) * int(n))
+
+    @classmethod
     def from_matmat(cls, n: int, matmat):
         """A black-box operator from the caller's products: ``matmat(X, trans)`` gets a
         column-major CUDA float64 tensor X (n x ncols) and returns A X (or A* X when

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblrtag.so")
-SOURCES = ["plan.cpp", "bn.cpp", "kernels.hip", "kernels_lp.hip", "blackbox.hip", "truncate.hip", "api.hip",
+SOURCES = ["plan.cpp", "bn.cpp", "kernels.hip", "kernels_lp.hip", "blackbox.hip", "truncate.hip", "slab.hip", "api.hip",
            "server.cpp"]
 ARCH = "gfx950"
 

@@ -326,6 +326,7 @@ PlanData::~PlanData() {
 OpData::~OpData() {
     dfree(pts);
     dfree(pts32);
+    if (ctx_free && ctx) ctx_free(ctx);
 }
 
 UblrData::~UblrData() {
@@ -489,6 +490,21 @@ blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_
         d->fn = apply;
         d->ctx = ctx;
         d->device = current_device();
+        auto* o = new blr_operator;
+        o->d = std::move(d);
+        *out = o;
+    });
+}
+
+blr_status blr_op_slab_create(int32_t n, int32_t l, double kappa_h, const int64_t* perm, blr_operator** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        if (!out) fail(BLR_ERR_INVALID_ARG, "NULL argument");
+        auto d = std::make_unique<OpData>();
+        d->type = OpType::Callback;
+        d->n = static_cast<int64_t>(n) * n;
+        d->device = current_device();
+        d->ctx = slab_create(n, l, kappa_h, perm, d->n, &d->fn, &d->ctx_free);
         auto* o = new blr_operator;
         o->d = std::move(d);
         *out = o;

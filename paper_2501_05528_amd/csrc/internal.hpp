@@ -76,6 +76,11 @@ inline int64_t result_bytes(const PlanData& P) {
     return static_cast<int64_t>(sizeof(double)) * (2 * P.n * P.k + bk * bk + P.b_values);
 }
 
+// Thin-slab Schur complement operator (slab.hip): a library-owned black box.  Returns its
+// context and sets the product callback and the context's release function.
+void* slab_create(int n, int l, double kappa_h, const int64_t* perm, int64_t N, blr_apply_fn* fn,
+                  void (**free_fn)(void*));
+
 // Host planner (plan.cpp).
 std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params* prm);
 int tag_columns(const blr_geometry* g, int extra);
@@ -99,6 +104,7 @@ struct OpData {
     float* pts32 = nullptr;       // kernel: the same points in FP32, owned
     blr_apply_fn fn = nullptr;    // callback: the caller's products with A and A*
     void* ctx = nullptr;          // callback: the caller's context, borrowed
+    void (*ctx_free)(void*) = nullptr;  // set when the library owns ctx (built-in black boxes)
     int device = -1;
     ~OpData();
 };
