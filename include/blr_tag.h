@@ -192,10 +192,27 @@ typedef int32_t (*blr_apply_fn)(void* ctx, int32_t trans, int64_t ncols, const d
  * apply -- 2 ell r columns for the sketches (Alg. 2), b k for the cores
  * (Table 1 step 2, in chunks of boxes) and 3^d m_max for the near-field
  * probes (Table 1 step 3).  ctx is borrowed and must outlive the operator.
- * The mixed-precision modes and blr_error_fro (which need entry access) return
- * BLR_ERR_UNSUPPORTED for such operators.
+ * In the mixed-precision modes the low-precision tagged sketch uses the
+ * optional FP32-operand products (blr_op_callback_set_lp), else the FP64
+ * products rounded to FP32; the refinement sketch applies A and A* to
+ * block-diagonal test columns (b r per side, in chunks of boxes) and sums each
+ * row box's far blocks.  blr_error_fro and batches, which need entry access,
+ * return BLR_ERR_UNSUPPORTED for such operators.
  */
 blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_operator** out);
+
+/*
+ * Low-precision products for the mixed-precision modes: apply_lp must enqueue
+ * Y = A X (trans = 0) or A* X (trans = 1) on `stream` with X, Y FP32 device
+ * arrays (n x ncols, ldx, ldy >= n), computing in `precision`
+ * (BLR_PREC_FP32_REFINE: FP32 arithmetic; BLR_PREC_BF16_REFINE: BF16 operands
+ * with FP32 accumulation, or anything at least as accurate), and return 0 or
+ * nonzero (BLR_ERR_OPERATOR).  Optional; NULL removes it.  Only for operators
+ * made by blr_op_callback_create.
+ */
+typedef int32_t (*blr_apply_lp_fn)(void* ctx, int32_t trans, int32_t precision, int64_t ncols, const float* X,
+                                   int64_t ldx, float* Y, int64_t ldy, void* stream);
+blr_status blr_op_callback_set_lp(blr_operator* op, blr_apply_lp_fn apply_lp);
 
 /*
  * The thin-slab Schur complement of Section 7.2 as a library-held black box

@@ -76,6 +76,8 @@ BATCH_AUTOTUNE = 2
 # int32 apply(ctx, trans, ncols, X, ldx, Y, ldy, stream): the black-box operator callback
 APPLY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p)
+APPLY_LP_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int32, c_int64, c_void_p, c_int64, c_void_p,
+                               c_int64, c_void_p)
 
 # name -> (restype, argtypes); every symbol declared in include/blr_tag.h
 SIGNATURES = {
@@ -92,6 +94,7 @@ SIGNATURES = {
     "blr_op_kernel_create": (c_int32, [c_int32, c_int32, c_int64, P_f64, POINTER(c_void_p)]),
     "blr_op_slab_create": (c_int32, [c_int32, c_int32, c_double, P_i64, POINTER(c_void_p)]),
     "blr_op_callback_create": (c_int32, [c_int64, APPLY_FN, c_void_p, POINTER(c_void_p)]),
+    "blr_op_callback_set_lp": (c_int32, [c_void_p, APPLY_LP_FN]),
     "blr_op_destroy": (None, [c_void_p]),
     "blr_op_apply": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                c_void_p]),

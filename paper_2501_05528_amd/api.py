@@ -200,11 +200,12 @@ class Operator:
         return cls(h, int(n) * int(n))
 
     @classmethod
-    def from_matmat(cls, n: int, matmat):
+    def from_matmat(cls, n: int, matmat, matmat_lp=None):
         """A black-box operator from the caller's products: ``matmat(X, trans)`` gets a
         column-major CUDA float64 tensor X (n x ncols) and returns A X (or A* X when
         ``trans``) as a tensor of the same shape.  The library calls it on its stream
-        (made current here) for every product it needs."""
+        (made current here) for every product it needs.  ``matmat_lp(X, trans, precision)``
+        (optional, mixed modes) gets and returns float32 tensors, precision "fp32" or "bf16"."""
         torch = _torch()
 
         def _apply(ctx, trans, ncols, xp, ldx, yp, ldy, stream):
@@ -226,7 +227,29 @@ class Operator:
         fn = _lib.APPLY_FN(_apply)
         h = c_void_p()
         check(lib().blr_op_callback_create(n, fn, None, byref(h)))
-        return cls(h, n, keep=fn)
+        if matmat_lp is None:
+            return cls(h, n, keep=fn)
+        names = {v: k for k, v in PRECISIONS.items()}
+
+        def _apply_lp(ctx, trans, precision, ncols, xp, ldx, yp, ldy, stream):
+            try:
+                X = torch.as_tensor(_DeviceView(xp, n, ncols, 4, ldx), device="cuda")
+                Y = torch.as_tensor(_DeviceView(yp, n, ncols, 4, ldy), device="cuda")
+                prec = names[int(precision)]
+                if stream:
+                    with torch.cuda.stream(torch.cuda.ExternalStream(stream)):
+                        Y.copy_(matmat_lp(X, bool(trans), prec))
+                else:
+                    Y.copy_(matmat_lp(X, bool(trans), prec))
+                    torch.cuda.synchronize()
+                return 0
+            except Exception:  # reported to the caller as BLR_ERR_OPERATOR
+                return 1
+
+        fn_lp = _lib.APPLY_LP_FN(_apply_lp)
+        op = cls(h, n, keep=(fn, fn_lp))
+        check(lib().blr_op_callback_set_lp(h, fn_lp))
+        return op
 
     def apply(self, X, trans: bool = False, stream=None):
         Y = colmajor_empty(self.n, X.shape[1], X.device)

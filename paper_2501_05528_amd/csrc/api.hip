@@ -496,6 +496,14 @@ blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_
     });
 }
 
+blr_status blr_op_callback_set_lp(blr_operator* op, blr_apply_lp_fn apply_lp) {
+    return guard([&] {
+        if (!op || !op->d) fail(BLR_ERR_INVALID_ARG, "NULL operator");
+        if (op->d->type != OpType::Callback) fail(BLR_ERR_INVALID_ARG, "not a callback operator");
+        op->d->fn_lp = apply_lp;
+    });
+}
+
 blr_status blr_op_slab_create(int32_t n, int32_t l, double kappa_h, const int64_t* perm, blr_operator** out) {
     if (out) *out = nullptr;
     return guard([&] {
@@ -625,6 +633,57 @@ double refine_flops(const PlanData& P) {
     return 4.0 * P.r * f;
 }
 
+// Low-precision tagged sketch (mixed modes) through a black box: the caller's FP32-operand
+// products when it offers them, else its FP64 products rounded to FP32.
+void sketch_lp_blackbox(const OpData& o, const PlanData& P, const DeviceTables& t, int precision, int r_lo,
+                        const double* G, const double* H, float* Y0, float* Z0, hipStream_t s, AsyncTemps& tmp) {
+    const int64_t LR = static_cast<int64_t>(P.ell) * r_lo;
+    const int64_t nf = (P.n * LR + 1) / 2;
+    if (o.fn_lp) {
+        float* Om = reinterpret_cast<float*>(tmp.plain(nf));
+        float* Yo = reinterpret_cast<float*>(tmp.plain(nf));
+        for (int side = 0; side < 2; ++side) {
+            launch_expand_tagged_f32(P, t, side ? H : G, r_lo, Om, s);
+            const int32_t rc = o.fn_lp(o.ctx, side, precision, LR, Om, P.n, Yo, P.n, static_cast<void*>(s));
+            if (rc != 0) {
+                std::ostringstream os;
+                os << "operator low-precision apply returned " << rc;
+                fail(BLR_ERR_OPERATOR, os.str());
+            }
+            HIPC(hipMemcpyAsync(side ? Z0 : Y0, Yo, P.n * LR * sizeof(float), hipMemcpyDeviceToDevice, s));
+        }
+        return;
+    }
+    double* Om = tmp.plain(P.n * LR);
+    double* Yo = tmp.plain(P.n * LR);
+    for (int side = 0; side < 2; ++side) {
+        launch_expand_tagged_w(P, t, side ? H : G, r_lo, Om, s);
+        op_apply(o, side, LR, Om, P.n, Yo, P.n, s);
+        launch_to_f32(Yo, P.n * LR, side ? Z0 : Y0, s);
+    }
+}
+
+// Refinement sketch through a black box: A (or A*) applied to block-diagonal test columns
+// (the mixing blocks X_l of every box, in chunks of boxes), then the far blocks of each
+// row box summed: S(I_i) = sum_{l in F_i} A_il X_l (2 b r columns over both sides).
+void refine_blackbox(const OpData& o, const PlanData& P, const DeviceTables& t, const double* Xv,
+                     const double* Xu, double* SY, double* SZ, hipStream_t s, AsyncTemps& tmp) {
+    const int cb = boxes_per_chunk(P, P.r);
+    double* X = tmp.plain(P.n * static_cast<int64_t>(cb) * P.r);
+    double* W = tmp.plain(P.n * static_cast<int64_t>(cb) * P.r);
+    for (int side = 0; side < 2; ++side) {
+        const double* Xs = side ? Xu : Xv;
+        double* S = side ? SZ : SY;
+        launch_fill0(S, P.n * P.r, s);
+        for (int j0 = 0; j0 < P.b; j0 += cb) {
+            const int j1 = std::min(P.b, j0 + cb);
+            launch_embed_blockdiag(P, t, Xs, P.r, j0, j1, X, s);
+            op_apply(o, side, static_cast<int64_t>(j1 - j0) * P.r, X, P.n, W, P.n, s);
+            launch_far_gather(P, t, W, P.r, j0, j1, S, s);
+        }
+    }
+}
+
 }  // namespace
 
 blr_status blr_sketch_lowp(const blr_plan* plan, const blr_operator* op, int32_t precision,
@@ -634,12 +693,15 @@ blr_status blr_sketch_lowp(const blr_plan* plan, const blr_operator* op, int32_t
         const PlanData& P = plan_of(plan);
         const OpData& o = op_of(op, P);
         if (!is_mixed(precision)) fail(BLR_ERR_INVALID_ARG, "precision must be a mixed mode");
-        require_entries(o, "the low-precision sketch");
         check_r_lo(P, r_lo);
         if (!G || !H || !Y0 || !Z0) fail(BLR_ERR_INVALID_ARG, "NULL G, H, Y0 or Z0");
         const DeviceTables& t = plan->d->tables();
         hipStream_t s = static_cast<hipStream_t>(stream);
         AsyncTemps tmp(s);
+        if (is_callback(o)) {
+            sketch_lp_blackbox(o, P, t, precision, r_lo, G, H, Y0, Z0, s, tmp);
+            return;
+        }
         void* PG = pack_lp(tmp, P, t, precision, r_lo, G, s);
         void* PH = pack_lp(tmp, P, t, precision, r_lo, H, s);
         launch_sketch_lp(o, P, t, precision, r_lo, PG, PH, Y0, Z0, s);
@@ -679,7 +741,6 @@ blr_status blr_refine_sketch(const blr_plan* plan, const blr_operator* op, int32
         const OpData& o = op_of(op, P);
         check_r_lo(P, r_lo);
         if (!U0 || !V0 || !gamma_u || !gamma_v || !SY || !SZ) fail(BLR_ERR_INVALID_ARG, "NULL argument");
-        require_entries(o, "the refinement sketch");
         const DeviceTables& t = plan->d->tables();
         hipStream_t s = static_cast<hipStream_t>(stream);
         AsyncTemps tmp(s);
@@ -687,7 +748,8 @@ blr_status blr_refine_sketch(const blr_plan* plan, const blr_operator* op, int32
         double* Xu = tmp.get(P.n * P.r);
         launch_mix(P, t, r_lo, V0, gamma_v, Xv, s);
         launch_mix(P, t, r_lo, U0, gamma_u, Xu, s);
-        launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
+        if (is_callback(o)) refine_blackbox(o, P, t, Xv, Xu, SY, SZ, s, tmp);
+        else launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
     });
 }
 
@@ -710,7 +772,6 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
         if (mixed) {
             check_r_lo(P, r_lo);
             if (!O.gamma_u || !O.gamma_v) fail(BLR_ERR_INVALID_ARG, "mixed modes need gamma_u and gamma_v");
-            require_entries(o, "the mixed-precision modes");
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         const DeviceTables& t = plan->d->tables();
@@ -792,9 +853,13 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
             double* SY = tmp.get(P.n * P.r);
             double* SZ = tmp.get(P.n * P.r);
             mark(0);
-            void* PG = pack_lp(tmp, P, t, O.precision, r_lo, G, s);
-            void* PH = pack_lp(tmp, P, t, O.precision, r_lo, H, s);
-            launch_sketch_lp(o, P, t, O.precision, r_lo, PG, PH, Y0, Z0, s);
+            if (is_callback(o)) {
+                sketch_lp_blackbox(o, P, t, O.precision, r_lo, G, H, Y0, Z0, s, tmp);
+            } else {
+                void* PG = pack_lp(tmp, P, t, O.precision, r_lo, G, s);
+                void* PH = pack_lp(tmp, P, t, O.precision, r_lo, H, s);
+                launch_sketch_lp(o, P, t, O.precision, r_lo, PG, PH, Y0, Z0, s);
+            }
             mark(1);
             launch_postprocess_lp(P, t, r_lo, Y0, Yh, s);
             launch_postprocess_lp(P, t, r_lo, Z0, Zh, s);
@@ -811,7 +876,8 @@ blr_status blr_tag_compress(const blr_plan* plan, const blr_operator* op, const 
                 keep_copy(h->V0, V0, P.n * r_lo);
             }
             mark(3);
-            launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
+            if (is_callback(o)) refine_blackbox(o, P, t, Xv, Xu, SY, SZ, s, tmp);
+            else launch_refine(o, P, t, Xv, Xu, SY, SZ, s);
             mark(4);
             if (keep) {
                 keep_copy(h->SY, SY, P.n * P.r);

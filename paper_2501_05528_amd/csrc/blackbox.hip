@@ -31,6 +31,49 @@ __global__ __launch_bounds__(256) void k_expand_tagged(const double* __restrict_
     Om[idx] = T[static_cast<int64_t>(rb[row]) * ell + s] * G[row + static_cast<int64_t>(c) * n];
 }
 
+// The same tagged test matrix with w columns per tag column, rounded to FP32 (the
+// operand of a caller's low-precision products).
+__global__ __launch_bounds__(256) void k_expand_tagged_f32(const double* __restrict__ G, int64_t n, int w,
+                                                           int ell, const double* __restrict__ T,
+                                                           const int32_t* __restrict__ rb,
+                                                           float* __restrict__ Om) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = n * static_cast<int64_t>(ell) * w;
+    if (idx >= total) return;
+    const int64_t col = idx / n;
+    const int64_t row = idx - col * n;
+    const int s = static_cast<int>(col / w), c = static_cast<int>(col - static_cast<int64_t>(s) * w);
+    Om[idx] = static_cast<float>(T[static_cast<int64_t>(rb[row]) * ell + s] * G[row + static_cast<int64_t>(c) * n]);
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx < n) y[idx] = static_cast<float>(x[idx]);
+}
+
+__global__ __launch_bounds__(256) void k_fill0(double* __restrict__ x, int64_t n) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx < n) x[idx] = 0.0;
+}
+
+// S(row, c) += sum over boxes l in [j0, j1) that are far from box(row), in ascending order,
+// of W(row, (l - j0) w + c): the far-field part of the products of A with a chunk of
+// block-diagonal test columns (w columns per box).
+__global__ __launch_bounds__(256) void k_far_gather(const double* __restrict__ W, int64_t n, int w,
+                                                    const int32_t* __restrict__ rb,
+                                                    const uint8_t* __restrict__ nearm, int nbox, int j0, int j1,
+                                                    double* __restrict__ S) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= n * w) return;
+    const int64_t c = idx / n;
+    const int64_t row = idx - c * n;
+    const int64_t i = rb[row];
+    double acc = S[idx];
+    for (int l = j0; l < j1; ++l)
+        if (!nearm[i * nbox + l]) acc += W[row + (static_cast<int64_t>(l - j0) * w + c) * n];
+    S[idx] = acc;
+}
+
 // X(:, (j - j0) w + t) = S(:, t) on the rows of box j, zero elsewhere, for boxes
 // j0 <= j < j1 (a column chunk of blkdiag(S_1, ..., S_b) with w columns per box).
 __global__ __launch_bounds__(256) void k_embed_blockdiag(const double* __restrict__ S, int64_t n, int w,
@@ -189,6 +232,40 @@ void launch_expand_tagged(const PlanData& P, const DeviceTables& t, const double
     hipLaunchKernelGGL(k_expand_tagged, dim3(blocks_for(total)), dim3(256), 0, s, G, P.n, P.r, P.ell, t.T,
                        t.row_box, Om);
     check_launch_bb("tagged test matrix");
+}
+
+void launch_expand_tagged_f32(const PlanData& P, const DeviceTables& t, const double* G, int w, float* Om,
+                              hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(P.ell) * w;
+    hipLaunchKernelGGL(k_expand_tagged_f32, dim3(blocks_for(total)), dim3(256), 0, s, G, P.n, w, P.ell, t.T,
+                       t.row_box, Om);
+    check_launch_bb("FP32 tagged test matrix");
+}
+
+void launch_expand_tagged_w(const PlanData& P, const DeviceTables& t, const double* G, int w, double* Om,
+                            hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(P.ell) * w;
+    hipLaunchKernelGGL(k_expand_tagged, dim3(blocks_for(total)), dim3(256), 0, s, G, P.n, w, P.ell, t.T,
+                       t.row_box, Om);
+    check_launch_bb("tagged test matrix");
+}
+
+void launch_to_f32(const double* x, int64_t n, float* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(256), 0, s, x, n, y);
+    check_launch_bb("FP32 rounding");
+}
+
+void launch_fill0(double* x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill0, dim3(blocks_for(n)), dim3(256), 0, s, x, n);
+    check_launch_bb("fill");
+}
+
+void launch_far_gather(const PlanData& P, const DeviceTables& t, const double* W, int w, int j0, int j1,
+                       double* S, hipStream_t s) {
+    const int64_t total = P.n * static_cast<int64_t>(w);
+    hipLaunchKernelGGL(k_far_gather, dim3(blocks_for(total)), dim3(256), 0, s, W, P.n, w, t.row_box, t.nearm,
+                       P.b, j0, j1, S);
+    check_launch_bb("far-field gather");
 }
 
 void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const double* S, int w, int j0,

@@ -103,6 +103,7 @@ struct OpData {
     double* pts = nullptr;        // kernel: device SoA [3][n] (unused axes zero), owned
     float* pts32 = nullptr;       // kernel: the same points in FP32, owned
     blr_apply_fn fn = nullptr;    // callback: the caller's products with A and A*
+    blr_apply_lp_fn fn_lp = nullptr;  // callback: optional FP32-operand products (mixed modes)
     void* ctx = nullptr;          // callback: the caller's context, borrowed
     void (*ctx_free)(void*) = nullptr;  // set when the library owns ctx (built-in black boxes)
     int device = -1;

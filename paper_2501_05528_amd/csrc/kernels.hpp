@@ -87,6 +87,18 @@ void launch_expand_tagged(const PlanData& P, const DeviceTables& t, const double
                           hipStream_t s);
 void launch_embed_blockdiag(const PlanData& P, const DeviceTables& t, const double* S, int w, int j0,
                             int j1, double* X, hipStream_t s);
+// Mixed precision on a black box: the tagged test matrix with w columns per tag column in
+// FP64 or rounded to FP32, FP64 -> FP32 rounding, zero fill, and the far-field gather
+// S(row, :) += sum_{l in [j0, j1), l far from box(row)} W(row, block l) of products with
+// block-diagonal test columns.
+void launch_expand_tagged_w(const PlanData& P, const DeviceTables& t, const double* G, int w, double* Om,
+                            hipStream_t s);
+void launch_expand_tagged_f32(const PlanData& P, const DeviceTables& t, const double* G, int w, float* Om,
+                              hipStream_t s);
+void launch_to_f32(const double* x, int64_t n, float* y, hipStream_t s);
+void launch_fill0(double* x, int64_t n, hipStream_t s);
+void launch_far_gather(const PlanData& P, const DeviceTables& t, const double* W, int w, int j0, int j1,
+                       double* S, hipStream_t s);
 // Alg. 3 on a black box: masked test matrices of boxes [i0, i1) (N x (i1 - i0) r) and
 // each box's own rows of their products.
 void launch_expand_masked(const PlanData& P, const DeviceTables& t, const double* G, int i0, int i1,

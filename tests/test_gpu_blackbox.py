@@ -6,7 +6,8 @@ caller's products (Python callback running a dense product on the library's stre
 * Results against the oracle (same tolerances as tests/test_gpu_parity.py): the
   sketches to 1e-12, every far block U_i Atil_ij V_j* and near block plus B_ij to
   1e-11 max|A|, and the power estimate of ||A - A_uBLR||_2 in the 1.5 band.
-* Modes that need entry access are refused with BLR_ERR_UNSUPPORTED.
+* The exact Frobenius error, which needs entry access, is refused with BLR_ERR_UNSUPPORTED
+  (the mixed-precision modes through a black box are tested in test_gpu_blackbox_mixed.py).
 * The host export returns the same arrays as the device parts.
 """
 import numpy as np
@@ -119,16 +120,9 @@ def test_power_error_vs_oracle(run):
 
 
 def test_entry_access_modes_refused(run):
-    import torch
-    P, plan, op, g = run["P"], run["plan"], run["op"], run["g"]
+    P, op = run["P"], run["op"]
     with pytest.raises(P.BlrError) as ei:
         run["h"].error_fro(op)
-    assert ei.value.name == "BLR_ERR_UNSUPPORTED"
-    r = plan.r
-    G = P.colmajor(np.ones((g.n, r)))
-    gam = torch.zeros((plan.b, r, r), dtype=torch.float64, device="cuda")
-    with pytest.raises(P.BlrError) as ei:
-        P.compress(plan, op, G, G, precision="bf16", gamma_u=gam, gamma_v=gam)
     assert ei.value.name == "BLR_ERR_UNSUPPORTED"
 
 
