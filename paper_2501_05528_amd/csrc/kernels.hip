@@ -404,7 +404,7 @@ void gemm_launch(AS A, BS B, OUT O, int64_t M, int64_t K, int ncols, hipStream_t
 // ------------------------------------------------------------ tagged sketch
 // Y(:, s*r + c) = sum_l T(l, s) A(:, I_l) G(I_l, c)  (and Z from H), i.e.
 // Y = A Omega with Omega from eq. extend_test_mat.  The K loop walks the
-// source boxes l in steps of KT rows that never straddle a box, so within a
+// source boxes l in steps of KT (32) rows that never straddle a box, so within a
 // step the tag weight T(l, s) is one scalar per tag column s: it scales the
 // MFMA A fragments of the generated kernel tile, and the B tile is the plain
 // rows of [G | H] (r columns each, padded to 16*NTR).
@@ -425,7 +425,7 @@ __device__ inline double mfma44(double a, double b, double c) {
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <class AS, int NTR, int NSIDE, int SVW>
+template <class AS, int NTR, int NSIDE, int SVW, int KT>
 __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restrict__ T,
                                                     const int64_t* __restrict__ box_ptr, int nbox,
                                                     const double* __restrict__ G0,
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     __shared__ __attribute__((aligned(16))) double s_ltab[256];
     A.prepare((BLR_LDS double*)s_ltab);
     __syncthreads();
-    constexpr int MA = 2, BM = 4 * MA, KT = 16, CW = NTR * 16;  // rows, sources/step, cols/side
+    constexpr int MA = 2, BM = 4 * MA, CW = NTR * 16;            // rows, cols/side (KT sources/step)
     constexpr int BW = NSIDE * CW;                               // B tile width
     constexpr int BPT = (KT * BW + 255) / 256;
     constexpr int AGEN = BM * KT;                                // A tile entries per step
@@ -604,8 +604,8 @@ void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double*
     const int svw = std::max(1, std::min(8, 48 / acc_per_sv));
     const int groups = (P.ell + 4 * svw - 1) / (4 * svw);
     dim3 grid((P.n + 7) / 8, groups);
-#define BLR_SKETCH_CASE(NTRV, NSV, SVWV)                                                         \
-    hipLaunchKernelGGL((k_sketch<AS, NTRV, NSV, SVWV>), grid, dim3(256), 0, s, A, t.T, t.box_ptr, \
+#define BLR_SKETCH_CASE(NTRV, NSV, SVWV)                                                             \
+    hipLaunchKernelGGL((k_sketch<AS, NTRV, NSV, SVWV, 32>), grid, dim3(256), 0, s, A, t.T, t.box_ptr, \
                        P.b, G0, G1, P.n, P.r, P.ell, Y0, Y1)
     if (nside == 2) {
         switch (ntr) {
