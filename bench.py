@@ -172,16 +172,17 @@ def basic_section(S, tag_value, with_error):
             "sample_TFLOPs": round(sk, 2), "sample_flops": rep["sketch_flops"]}
 
 
-def paper_geometry_section(cases=((20000, 6), (100000, 7)), k=50, p=10, steps=3, seed=20250108):
-    """The geometry of the paper's experiments (Section 7): N uniformly random points in the
-    unit square, median-split boxes (b = 64 and 128 for N = 20000 and 100000, close to the
-    paper's b = sqrt(9 N / k) at k = 30), neighbours sharing a boundary, log kernel, k = 50 (for
-    errors near 1e-8), FP64."""
+def paper_geometry_section(cases=((20000, 77), (100000, 173)), k=30, p=10, steps=3, seed=20250108):
+    """The geometry and parameters of the paper's 2D Laplace experiments (Section 7.1): N
+    uniformly random points in the unit square, b = sqrt(3^d N / k) boxes (77 and 173 at
+    N = 20000 and 100000) of N / b points up to one from median-type splits, neighbours that
+    share a boundary, log kernel, k = 30, p = 10, 3 extra tag columns, FP64.  Reports the total
+    products of a compression against N (the paper prints 8.3 times fewer at N = 100000)."""
     import torch
     import paper_2501_05528_amd as P
     out = {}
-    for n, levels in cases:
-        g, near, _ = W.kd_geometry(n, 2, levels, seed)
+    for n, nb in cases:
+        g, near, _ = W.kd_geometry(n, 2, 0, seed, nboxes=nb)
         ell = P.tag_columns(g.box_ptr, None, 3, near=near)
         T = W.tag_matrix(seed, g.nboxes, ell)
         G, H = W.gaussian_test_blocks(seed, g.n, k + p)
@@ -198,11 +199,14 @@ def paper_geometry_section(cases=((20000, 6), (100000, 7)), k=50, p=10, steps=3,
         el = (time.perf_counter() - t0) / steps
         err = h.error_fro(op)
         sizes = g.box_sizes()
-        log(f"paper geometry N={n}: {1e3 * el:.1f} ms, rel err {err:.2e}")
+        applies = int(rep["applies_A"] + rep["applies_At"])
+        log(f"paper geometry N={n}, b={nb}: {1e3 * el:.1f} ms, {applies} products, rel err {err:.2e}")
         out[f"n{n}"] = {"value": round(1.0 / el, 4), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 3),
-                        "boxes": g.nboxes, "m_min": int(sizes.min()), "m_max": int(sizes.max()), "ell": ell,
-                        "ncolours": plan.info["ncolours"],
-                        "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+                        "boxes": g.nboxes, "k": k, "p": p, "m_min": int(sizes.min()), "m_max": int(sizes.max()),
+                        "ell": ell, "ncolours": plan.info["ncolours"],
+                        "applies_step1": int(2 * rep["applies_At"]),
+                        "applies_per_compression": applies,
+                        "N_over_applies": round(n / applies, 2),
                         "rel_err_fro": err,
                         "sketch_TFLOPs": round(rep["sketch_flops"] / (rep["ms_sketch"] * 1e-3) / 1e12, 2)}
         del h, plan, op
@@ -214,7 +218,7 @@ def bn_section(cases=((8, 8), (16, 16)), q=8, k=16, p=10, seed=20250109):
     q x q = 64 points (k = 16), with the same plan and operator: products, time and
     error.  Block nullification sketches s = r + 9 m columns per side and needs a
     Householder QR of an s x (up to 9 m) block of the test matrix per box and side
-    (host FP64, the post-processing cost of Section 3.2)."""
+    (on the GPU; the post-processing cost of Section 3.2)."""
     import torch
     import paper_2501_05528_amd as P
     out = {}
@@ -252,7 +256,10 @@ def bn_section(cases=((8, 8), (16, 16)), q=8, k=16, p=10, seed=20250109):
             "tagging": {"ms_per_step": round(1e3 * tt, 3), "applies_per_compression": int(rt["applies_A"] + rt["applies_At"]),
                         "ms_sketch": round(rt["ms_sketch"], 3), "ms_postprocess": round(rt["ms_postprocess"], 3),
                         "rel_err_fro": et},
-            "tagging_speedup": round(tb / tt, 2)}
+            "tagging_speedup": round(tb / tt, 2),
+            "note": "both methods run on the GPU: products, block nullification's per-box null "
+                    "spaces (one Householder QR per box and side) and projections, tagging's "
+                    "post-processing"}
     return out
 
 
@@ -278,6 +285,154 @@ def rank_section(S, tol=1e-8, k_probe=48, p=10):
         f"rel err {err:.2e}")
     return {"tol": tol, "k_probe": k_probe, "k": k, "ms_rank": round(1e3 * t_rank, 3),
             "ms_compress": round(rep["ms_total"], 3), "rel_err_fro": err}
+
+
+def truncation_section(S, tol=1e-8, k_big=48, p=10):
+    """Per-box ranks from a tolerance on the bench workload: compress at k = k_big, truncate
+    the representation to tol (blr_ublr_truncate), report the ranks, the change and the
+    exact error before and after."""
+    import torch
+    P, g, op, wl = S["P"], S["g"], S["op"], S["wl"]
+    ell = P.tag_columns(g.box_ptr, g.lattice, wl.extra_tag_cols)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    plan = P.Plan(g.box_ptr, g.lattice, k_big, T, p=p, extra_tag_cols=wl.extra_tag_cols)
+    G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(wl.seed, g.n, k_big + p))
+    h, rep = P.compress(plan, op, G, H, report=True)
+    h2, _, _, _ = h.truncate(tol)
+    del h2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h2, ku, kv, change = h.truncate(tol)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t0
+    e0 = h.error_fro(op)
+    e1 = h2.error_fro(op)
+    log(f"truncation to {tol:.0e}: ranks {ku.mean():.2f}/{kv.mean():.2f} of {k_big}, {1e3 * t_tr:.1f} ms, "
+        f"error {e0:.2e} -> {e1:.2e}")
+    return {"tol": tol, "k": k_big, "ms_compress": round(rep["ms_total"], 3), "ms_truncate": round(1e3 * t_tr, 3),
+            "mean_rank_u": round(float(ku.mean()), 3), "mean_rank_v": round(float(kv.mean()), 3),
+            "min_rank": int(min(ku.min(), kv.min())), "max_rank": int(max(ku.max(), kv.max())),
+            "rel_change": change, "rel_err_fro_before": e0, "rel_err_fro_after": e1}
+
+
+def slab_section(cases=((4, 24), (13, 24)), l=10, k=30, p=10, steps=2, seed=20250110):
+    """The paper's second workload (Section 7.2): the thin-slab Helmholtz Schur complement
+    as a library-held black box (products only), frontal face n x n in B x B boxes of
+    24 x 24 points, l = 10 planes, kappa h = 2 pi / 100, k = 30, p = 10, FP64.  Step (I)
+    products stay 2 ell r as N grows; the error is the paper's 20-step spectral estimate."""
+    import torch
+    import paper_2501_05528_amd as P
+    out = {}
+    for B, q in cases:
+        g, perm = W.slab_front(B, q)
+        n = B * q
+        ell = P.tag_columns(g.box_ptr, g.lattice, 3)
+        T = W.tag_matrix(seed, g.nboxes, ell)
+        G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(seed, g.n, k + p))
+        plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
+        op = P.Operator.slab(n, l, perm)
+        h, _ = P.compress(plan, op, G, H, report=True)
+        del h
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h, rep = P.compress(plan, op, G, H, report=True)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        x0 = W.gaussian_colmajor(seed, W.STREAM_POWER, g.n, 1)[:, 0]
+        e, a = h.error_power(op, P.colmajor(x0 / np.linalg.norm(x0)), iters=20)
+        log(f"slab N={g.n}: {1e3 * el:.1f} ms, spectral error {e / a:.2e}")
+        out[f"n{g.n}"] = {"value": round(1.0 / el, 4), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 3),
+                          "grid": [n, n, l], "boxes": g.nboxes, "m": q * q, "k": k, "ell": ell,
+                          "applies_step1": int(2 * rep["applies_At"]),
+                          "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+                          "stage_ms": {x: round(rep[x], 3) for x in ("ms_sketch", "ms_orth", "ms_cores",
+                                                                     "ms_nearfield", "ms_total")},
+                          "rel_err_2": e / a}
+        del h, plan, op
+    return out
+
+
+def config_section(S, steps=2, warmup=1, with_error=True):
+    """One workload in FP64 and both mixed modes: compressions/s, error and the rooflines of
+    the sketch (and of the refinement sketch in the mixed modes)."""
+    out = {}
+    for prec in ("fp64", "bf16", "fp32"):
+        m = run_mode(S, prec, steps, warmup, with_error)
+        m.pop("handle", None)
+        rp, st = m["rep"], m["stage"]
+        sk = rp["sketch_flops"] / (st["ms_sketch"] * 1e-3) / 1e12
+        d = {"value": round(m["value"], 4), "unit": "compressions/s", "ms_per_step": round(m["ms_step"], 3),
+             "rel_err_fro": m["err"], "applies_per_compression": int(rp["applies_A"] + rp["applies_At"]),
+             "stage_ms": {k: round(v, 3) for k, v in st.items()},
+             "sketch_roofline": {"bound": "mfma", "achieved": round(sk, 2), "peak": PEAK_TFLOPS[prec],
+                                 "unit": "TFLOP/s", "frac": round(sk / PEAK_TFLOPS[prec], 4),
+                                 "algorithmic_flops_per_launch": rp["sketch_flops"]}}
+        if prec != "fp64":
+            rf = rp["refine_flops"] / (st["ms_refine"] * 1e-3) / 1e12
+            d["refine_roofline"] = {"bound": "mfma", "achieved": round(rf, 2), "peak": PEAK_FP64_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(rf / PEAK_FP64_TFLOPS, 4),
+                                    "algorithmic_flops_per_launch": rp["refine_flops"]}
+        out[prec] = d
+    out["bf16_speedup_vs_fp64"] = round(out["bf16"]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
+def planted_section(steps=10):
+    """The planted exact-rank workload (64 x 64 grid, 8 x 8 boxes of 64, k = 8, dense A in
+    HBM): compressions/s and the exact error (exact recovery)."""
+    import torch
+    import paper_2501_05528_amd as P
+    wl = W.WORKLOADS["planted_2d_n4096"]
+    g = wl.geometry()
+    A, _, _ = W.planted_exact_rank(g, wl.k, wl.seed)
+    ell = P.tag_columns(g.box_ptr, g.lattice, wl.extra_tag_cols)
+    T = W.tag_matrix(wl.seed, g.nboxes, ell)
+    G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(wl.seed, g.n, wl.r))
+    plan = P.Plan(g.box_ptr, g.lattice, wl.k, T, p=wl.p, extra_tag_cols=wl.extra_tag_cols)
+    Ad = P.colmajor(A)
+    op = P.Operator.dense(Ad)
+    h, _ = P.compress(plan, op, G, H, report=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h, rep = P.compress(plan, op, G, H, report=True)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    return {"value": round(1.0 / el, 3), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 4),
+            "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+            "rel_err_fro": h.error_fro(op)}
+
+
+def _blas_threads():
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(d.get("num_threads", threads)) for d in info)
+    except Exception:
+        pass
+    return threads
+
+
+def cpu_baseline_planted():
+    """The whole oracle (reconstruct_tag with every step, then its exact error) on the
+    planted exact-rank workload, timed once in full."""
+    import oracle as O
+    wl = W.WORKLOADS["planted_2d_n4096"]
+    g = wl.geometry()
+    A, _, _ = W.planted_exact_rank(g, wl.k, wl.seed)
+    near = O.near_lists(g.lattice)
+    T = W.tag_matrix(wl.seed, g.nboxes, O.num_tag_columns(near, wl.extra_tag_cols))
+    G, H = W.gaussian_test_blocks(wl.seed, g.n, wl.r)
+    t0 = time.perf_counter()
+    res = O.reconstruct_tag(O.DenseOperator(A), g.box_ptr, g.lattice, wl.k, wl.p, wl.extra_tag_cols, T, G, H)
+    dt = time.perf_counter() - t0
+    err = O.rel_fro_error(O.DenseOperator(A), res["U"], res["V"], res["Atil"], res["B"], g.box_ptr, wl.k)
+    return {"value": round(1.0 / dt, 4), "unit": "compressions/s", "s": round(dt, 3), "kind": "oracle",
+            "sample": "full compression, timed once", "rel_err_fro": err,
+            "threads": {"blas": _blas_threads(), "python": 1}}
 
 
 def cpu_baseline(S, nsample_boxes=4):
@@ -328,17 +483,13 @@ def cpu_baseline(S, nsample_boxes=4):
     dt = time.perf_counter() - t0
     del At_rows
     per_comp = dt * g.nboxes / len(boxes)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    try:
-        from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        if info:
-            threads = max(int(d.get("num_threads", threads)) for d in info)
-    except Exception:
-        pass
+    threads = _blas_threads()
     return {"value": 1.0 / per_comp, "unit": "compressions/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(boxes)} of {g.nboxes} row boxes of every stage "
-                      f"({dt:.1f} s), extrapolated linearly to all row boxes"}
+                      f"({dt:.1f} s), extrapolated linearly to all row boxes (not a full timed run)",
+            "threads": {"blas": threads, "kernel_entries": 1},
+            "note": "products run in numpy's BLAS thread pool; kernel entries are generated "
+                    "by single-threaded numpy"}
 
 
 def _job_inputs(P, torch, wl, precision):
@@ -359,12 +510,13 @@ def _kw(j):
                                                     gamma_v=j["gamma_v"])
 
 
-def batch_section(njobs=24, seed=20250104, n_lo=4096, n_hi=32768):
+def batch_section(njobs=96, seed=20250104, n_lo=4096, n_hi=65536):
     """Uneven batch (the batch generator: N, box shape, rank, kernel per job): FP32-sketch
     mixed jobs in one batch (persistent sketch launches, HIP graph replay, autotuned
     tiles) against plain FP64 compressions one at a time, with the accuracy of each."""
     import torch
     import paper_2501_05528_amd as P
+    torch.cuda.empty_cache()
     wls = W.uneven_batch_jobs(njobs, seed, n_lo=n_lo, n_hi=n_hi)
     jobs64 = [_job_inputs(P, torch, wl, "fp64") for wl in wls]
     jobs32 = [dict(j, precision="fp32") for j in jobs64]
@@ -392,6 +544,8 @@ def batch_section(njobs=24, seed=20250104, n_lo=4096, n_hi=32768):
     ratio = max(e / max(f, 1e-300) for e, f in zip(emx, e64))
     sk = rep_eager["sketch_flops"] / (rep_eager["ms_sketch"] * 1e-3) / 1e12 if rep_eager["ms_sketch"] else None
     return {"jobs": njobs, "N_range": [min(j["n"] for j in jobs64), max(j["n"] for j in jobs64)],
+            "note": "N up to 65536: with N up to 131072 the 96 jobs' outputs and temporaries, which a "
+                    "batch keeps resident, need about 570 GB",
             "fp64_one_at_a_time_jobs_per_s": round(njobs / t64, 3),
             "batched_fp32_jobs_per_s": round(njobs / tb, 3),
             "speedup": round(t64 / tb, 3),
@@ -405,11 +559,15 @@ def batch_section(njobs=24, seed=20250104, n_lo=4096, n_hi=32768):
                                "jobs": rep_eager["class_jobs"]}}
 
 
-def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
-    """Poisson arrivals of a job mix in the BF16 mixed mode: jobs from the batch generator,
-    every fifth one the 2D Laplace N = 65536, k = 32 job and two the 2D Laplace N = 262144,
-    k = 48 job (32 x 32 boxes); a 4-slot server with HBM-budget admission against plain FP64
-    one at a time (1 slot), same arrivals."""
+def serve_section(rates=(10.0, 50.0, 200.0, 500.0), njobs=200, seed=20250105):
+    """Poisson arrivals of a job mix at several rates: 80 % jobs from the batch generator
+    (N 4096 .. 32768, three kernels, uneven boxes and ranks), 19 % the 2D Laplace N = 65536,
+    k = 32 job and 1 % the 2D Laplace N = 262144, k = 48 job (32 x 32 boxes).  Three drives of
+    the same arrivals: the 4-slot server in the BF16 mixed mode with HBM-budget admission,
+    BF16 one job at a time (1 slot), and plain FP64 one job at a time.  A client thread claims
+    results as they complete.  Latency is submit to completion; device overlap is the sum of
+    the jobs' device intervals over the span they cover."""
+    import threading
     import torch
     import paper_2501_05528_amd as P
     gen = W.uneven_batch_jobs(njobs, seed, n_lo=4096, n_hi=32768)
@@ -417,16 +575,33 @@ def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
     big = _job_inputs(P, torch, W.WORKLOADS["laplace2d_n262144"], "bf16")
     mix = []
     for q, wl in enumerate(gen):
-        if q % 24 == 11:
+        if q % 100 == 50:
             mix.append(big)
+        elif q % 5 == 4:
+            mix.append(lap)
         else:
-            mix.append(lap if q % 5 == 4 else _job_inputs(P, torch, wl, "bf16"))
+            mix.append(_job_inputs(P, torch, wl, "bf16"))
     torch.cuda.synchronize()
     rng = W.rng(seed, W.STREAM_ARRIVALS)
 
     def drive(gaps, precision, slots):
         srv = P.Server(hbm_budget=160 << 30, slots=slots)
-        tickets = []
+        tickets, stats = [], []
+        done = threading.Event()
+
+        def claim():
+            q = 0
+            while q < len(mix):
+                if q >= len(tickets):
+                    time.sleep(0.0005)
+                    continue
+                _, st = srv.wait(tickets[q])
+                stats.append(st)
+                q += 1
+            done.set()
+
+        th = threading.Thread(target=claim)
+        th.start()
         t = time.monotonic()
         t_first = t
         for j, gap in zip(mix, gaps):
@@ -435,24 +610,27 @@ def serve_section(rates=(20.0, 100.0), njobs=48, seed=20250105):
                 time.sleep(0.0002)
             jj = dict(j, precision=precision)
             tickets.append(srv.submit(jj["plan"], jj["op"], jj["G"], jj["H"], **_kw(jj)))
-        lat, t_last = [], t_first
-        for tk in tickets:
-            _, st = srv.wait(tk)
-            lat.append(st["t_end"] - st["t_submit"])
-            t_last = max(t_last, st["t_end"])
+        th.join()
         srv.close()
+        lat = [st["t_end"] - st["t_submit"] for st in stats]
+        t_last = max(st["t_end"] for st in stats)
+        busy = sum(st["dev_end_ms"] - st["dev_start_ms"] for st in stats)
+        span = max(st["dev_end_ms"] for st in stats) - min(st["dev_start_ms"] for st in stats)
         return {"jobs_per_s": round(len(mix) / (t_last - t_first), 3),
                 "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
-                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2)}
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+                "device_overlap": round(busy / span, 3) if span > 0 else None}
 
     nbig = sum(1 for j in mix if j is big)
     nlap = sum(1 for j in mix if j is lap)
-    out = {"jobs": len(mix), "mix": {"generator": len(mix) - nbig - nlap, "laplace2d_n65536": nlap,
-                                     "laplace2d_n262144": nbig},
+    out = {"jobs_per_rate": len(mix), "mix": {"generator": len(mix) - nbig - nlap, "laplace2d_n65536": nlap,
+                                              "laplace2d_n262144": nbig},
            "slots": 4, "admission": "FIFO by HBM footprint (160 GiB budget)"}
     for rate in rates:
-        gaps = rng.exponential(1.0 / rate, size=len(mix))   # the same arrivals for both
+        gaps = rng.exponential(1.0 / rate, size=len(mix))   # the same arrivals for all drives
+        log(f"serving at {rate:g} jobs/s")
         out[f"rate_{int(rate)}"] = {"served_bf16": drive(gaps, "bf16", 4),
+                                    "bf16_one_at_a_time": drive(gaps, "bf16", 1),
                                     "fp64_one_at_a_time": drive(gaps, "fp64", 1)}
     return out
 
@@ -477,6 +655,10 @@ def main():
                     help="skip the one-off Alg. 3 (basic randomized SVD) comparison run")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (BF16 / FP32 sketch + FP64 refinement) runs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 3D (N = 110592) and planted (N = 4096) workloads")
+    ap.add_argument("--no-truncate", action="store_true", help="skip the per-box rank truncation")
+    ap.add_argument("--no-slab", action="store_true", help="skip the thin-slab Schur complement")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(a plain kernel of known traffic for scaling rocprofv3 byte counters)")
@@ -556,6 +738,31 @@ def main():
                                     "algorithmic_flops_per_launch": rp["refine_flops"]},
             }
         out["mixed"] = mixed
+    if not args.no_configs:
+        try:
+            log("3D workload (1/r, N = 110592, k = 48): FP64, BF16 and FP32 mixed")
+            S3 = setup("invr3d_n110592")
+            out["invr3d_n110592"] = config_section(S3, with_error=not args.no_error)
+            del S3
+        except Exception as e:  # extra measurement: never lose the line
+            out["invr3d_n110592"] = {"error": repr(e)}
+        try:
+            log("planted exact-rank workload (N = 4096)")
+            out["planted_2d_n4096"] = planted_section()
+        except Exception as e:
+            out["planted_2d_n4096"] = {"error": repr(e)}
+    if not args.no_truncate:
+        try:
+            log("per-box ranks from a tolerance (truncation)")
+            out["truncation"] = truncation_section(S)
+        except Exception as e:
+            out["truncation"] = {"error": repr(e)}
+    if not args.no_slab:
+        try:
+            log("thin-slab Schur complement (black box)")
+            out["slab"] = slab_section()
+        except Exception as e:
+            out["slab"] = {"error": repr(e)}
     if not args.no_paper_geometry:
         try:
             log("random-point geometry of the paper's experiments")
@@ -595,6 +802,11 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(S)
+        try:
+            log("cpu baseline: full oracle run on the planted workload")
+            out["cpu_baseline"]["planted_2d_n4096_full"] = cpu_baseline_planted()
+        except Exception as e:
+            out["cpu_baseline"]["planted_2d_n4096_full"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

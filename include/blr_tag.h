@@ -429,11 +429,13 @@ blr_status blr_basic_compress(const blr_plan* plan, const blr_operator* op, cons
  * top-k left singular vectors of Y(I_i,:) P^(i), V_i likewise from Z and Psi.
  * Omega and Psi: device, N x s column-major, ld N; s >= blr_bn_min_columns
  * (r plus the rows of the largest neighbourhood, i.e. r + 3^d m on a uniform
- * tessellation) or BLR_ERR_INVALID_ARG.  The null vectors are computed on the
- * host from copies of Omega and Psi (the call synchronises the stream there);
- * a rank-deficient neighbour block gives BLR_ERR_NUMERICAL.  Report: applies_A
- * = s + b k + (colours) m_max, applies_At = s; ms_sketch covers the two
- * sketches, ms_postprocess the copies, null vectors and projections.
+ * tessellation; at most 2048 + r, else BLR_ERR_UNSUPPORTED) or
+ * BLR_ERR_INVALID_ARG.  The null vectors are computed on the device, one
+ * workgroup per box and side, in a stream-ordered workspace of b s (s - r)
+ * doubles; a rank-deficient neighbour block gives BLR_ERR_NUMERICAL (the call
+ * synchronises the stream to check).  Report: applies_A = s + b k + (colours)
+ * m_max, applies_At = s; ms_sketch covers the two sketches, ms_postprocess the
+ * null vectors and projections.
  * keep_samples != 0 keeps Y(I_i,:) P^(i) and Z(I_i,:) Q^(i) as BLR_PART_SY /
  * BLR_PART_SZ.  Ownership and errors as for blr_tag_compress (FP64, any operator).
  */

@@ -1095,16 +1095,17 @@ blr_status blr_bn_compress(const blr_plan* plan, const blr_operator* op, int64_t
         op_apply(o, 1, s, Psi, P.n, Z, P.n, st);
         mark(1);
         {
-            // the null vectors depend on the test matrices only: host Householder QRs
-            std::vector<double> hOm(static_cast<size_t>(ns)), hNull(static_cast<size_t>(P.b) * s * P.r);
-            for (int side = 0; side < 2; ++side) {
-                HIPC(hipMemcpyAsync(hOm.data(), side ? Psi : Omega, ns * sizeof(double), hipMemcpyDeviceToHost, st));
-                HIPC(hipStreamSynchronize(st));
-                bn_null_vectors(P, hOm.data(), s, hNull.data());
-                HIPC(hipMemcpyAsync(side ? dQ : dP, hNull.data(), hNull.size() * sizeof(double),
-                                    hipMemcpyHostToDevice, st));
-                HIPC(hipStreamSynchronize(st));
-            }
+            // the null vectors depend on the test matrices only: one Householder QR per box and side
+            double* wsp = tmp.get(bn_null_workspace_doubles(P, s));
+            double* flag = tmp.get(1);
+            launch_fill0(flag, 1, st);
+            launch_bn_null(P, t, Omega, s, wsp, dP, flag, st);
+            launch_bn_null(P, t, Psi, s, wsp, dQ, flag, st);
+            double hflag = 0.0;
+            HIPC(hipMemcpyAsync(&hflag, flag, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            if (hflag != 0.0)
+                fail(BLR_ERR_NUMERICAL, "a neighbour block of the test matrix is rank deficient (block nullification)");
         }
         launch_bn_project(P, t, Y, s, dP, SY, st);
         launch_bn_project(P, t, Z, s, dQ, SZ, st);

@@ -131,6 +131,131 @@ __global__ __launch_bounds__(256) void k_bn_project(const double* __restrict__ Y
     S[row + c * n] = acc;
 }
 
+__device__ inline double bb_wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Null vectors of Alg. 1 for one box per workgroup: M = Omega^(i)* (s x nrows, the rows of
+// the box's neighbours in ascending box order, built in the workspace), its Householder QR
+// (reflector sign that avoids cancellation, as LAPACK's), then P^(i) = the r columns of the
+// full orthogonal factor after its first nrows columns, formed by applying the reflectors in
+// reverse to unit vectors.  The reflector of column j is kept in place (rows >= j).
+// flag[0] is set to 1 if a neighbour block is numerically rank deficient.
+__global__ __launch_bounds__(256) void k_bn_null(const double* __restrict__ Om, int64_t n, int64_t s, int r,
+                                                 const int64_t* __restrict__ box_ptr,
+                                                 const int32_t* __restrict__ near_ptr,
+                                                 const int32_t* __restrict__ near_idx, int64_t ws_stride,
+                                                 double* __restrict__ work, double* __restrict__ Pall,
+                                                 double* __restrict__ flag) {
+    extern __shared__ double xs[];        // the current reflector, s doubles
+    __shared__ double vvs[2048];
+    __shared__ double hs[2];
+    constexpr int CB = 8;                 // columns a wave updates together (independent loads)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int box = blockIdx.x;
+    double* M = work + static_cast<int64_t>(box) * ws_stride;
+    // build M: column q = row q of Omega^(i)
+    int64_t nrows = 0;
+    for (int q = near_ptr[box]; q < near_ptr[box + 1]; ++q) {
+        const int j = near_idx[q];
+        const int64_t r0 = box_ptr[j], mj = box_ptr[j + 1] - r0;
+        for (int64_t e = tid; e < mj * s; e += 256) {
+            const int64_t u = e / s, t = e - u * s;
+            M[t + (nrows + u) * s] = Om[r0 + u + t * n];
+        }
+        nrows += mj;
+    }
+    __syncthreads();
+    const int nc = static_cast<int>(nrows);
+    double rmax = 0.0;
+    for (int j = 0; j < nc; ++j) {
+        double* x = M + static_cast<int64_t>(j) * s;
+        if (wave == 0) {
+            double s2 = 0.0;
+            for (int64_t a = j + lane; a < s; a += 64) s2 = fma(x[a], x[a], s2);
+            s2 = bb_wave_sum(s2);
+            if (lane == 0) {
+                const double nrm = sqrt(s2);
+                rmax = fmax(rmax, nrm);
+                const double x0 = x[j];
+                const double alpha = x0 >= 0.0 ? -nrm : nrm;
+                if (!(nrm > 1e-12 * rmax)) flag[0] = 1.0;
+                x[j] = x0 - alpha;
+                hs[0] = s2 - x0 * x0 + (x0 - alpha) * (x0 - alpha);
+            }
+        }
+        __syncthreads();
+        const double vv = hs[0];
+        if (tid == 0) vvs[j] = vv;
+        for (int64_t a = j + tid; a < s; a += 256) xs[a] = x[a];
+        __syncthreads();
+        for (int c0 = j + 1 + wave * CB; c0 < nc; c0 += 4 * CB) {
+            const int cn = min(CB, nc - c0);
+            double* y = M + static_cast<int64_t>(c0) * s;
+            double d[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) d[u] = 0.0;
+            for (int64_t a = j + lane; a < s; a += 64) {
+                const double xa = xs[a];
+#pragma unroll
+                for (int u = 0; u < CB; ++u)
+                    if (u < cn) d[u] = fma(xa, y[a + u * s], d[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) d[u] = bb_wave_sum(d[u]);
+            double f[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) f[u] = vv > 0.0 ? 2.0 * d[u] / vv : 0.0;
+            for (int64_t a = j + lane; a < s; a += 64) {
+                const double xa = xs[a];
+#pragma unroll
+                for (int u = 0; u < CB; ++u)
+                    if (u < cn) y[a + u * s] -= f[u] * xa;
+            }
+        }
+        __syncthreads();
+    }
+    // P^(i)(:, c) = H_0 ... H_{nc-1} e_{nc + c}: each wave applies every reflector (staged in
+    // LDS) to its columns together
+    double* Pb = Pall + static_cast<int64_t>(box) * s * r;
+    for (int idx = tid; idx < s * r; idx += 256) {
+        const int64_t c = idx / s, a = idx - c * s;
+        Pb[idx] = (a == nc + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = nc - 1; j >= 0; --j) {
+        const double* x = M + static_cast<int64_t>(j) * s;
+        for (int64_t a = j + tid; a < s; a += 256) xs[a] = x[a];
+        __syncthreads();
+        const double vv = vvs[j];
+        for (int c0 = wave * CB; c0 < r; c0 += 4 * CB) {
+            const int cn = min(CB, r - c0);
+            double* y = Pb + static_cast<int64_t>(c0) * s;
+            double d[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) d[u] = 0.0;
+            for (int64_t a = j + lane; a < s; a += 64) {
+                const double xa = xs[a];
+#pragma unroll
+                for (int u = 0; u < CB; ++u)
+                    if (u < cn) d[u] = fma(xa, y[a + u * s], d[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) d[u] = bb_wave_sum(d[u]);
+            for (int64_t a = j + lane; a < s; a += 64) {
+                const double xa = xs[a];
+#pragma unroll
+                for (int u = 0; u < CB; ++u)
+                    if (u < cn) y[a + u * s] -= (vv > 0.0 ? 2.0 * d[u] / vv : 0.0) * xa;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // X_c(box_ptr[l] + u, u) = 1 for every box l of colour c and u < m_l, zero elsewhere
 // (the sparse identity probe of Table 1 step 3), N x m_max.
 __global__ __launch_bounds__(256) void k_identity_probe(int64_t n, int m_max, const int32_t* __restrict__ rb,
@@ -299,6 +424,18 @@ void launch_bn_project(const PlanData& P, const DeviceTables& t, const double* Y
     hipLaunchKernelGGL(k_bn_project, dim3(blocks_for(total)), dim3(256), 0, s, Y, P.n, ns, P.r, t.row_box,
                        Pall, S);
     check_launch_bb("block-nullified samples");
+}
+
+int64_t bn_null_workspace_doubles(const PlanData& P, int64_t ns) {
+    return static_cast<int64_t>(P.b) * ns * (ns - P.r);
+}
+
+void launch_bn_null(const PlanData& P, const DeviceTables& t, const double* Om, int64_t ns, double* work,
+                    double* Pall, double* flag, hipStream_t s) {
+    if (ns - P.r > 2048) fail(BLR_ERR_UNSUPPORTED, "block nullification supports neighbourhoods of at most 2048 rows");
+    hipLaunchKernelGGL(k_bn_null, dim3(P.b), dim3(256), static_cast<size_t>(ns) * sizeof(double), s, Om, P.n, ns,
+                       P.r, t.box_ptr, t.near_ptr, t.near_idx, ns * (ns - P.r), work, Pall, flag);
+    check_launch_bb("block-nullification null vectors");
 }
 
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s) {

@@ -86,10 +86,8 @@ std::shared_ptr<PlanData> build_plan(const blr_geometry* g, const blr_tag_params
 int tag_columns(const blr_geometry* g, int extra);
 
 // Block nullification (bn.cpp): the smallest test-matrix width that leaves r null
-// vectors for every box, and the null vectors of every box (b x s x r, box-major,
-// each s x r column-major) from the host copy of the N x s test matrix.
+// vectors for every box.
 int64_t bn_min_columns(const PlanData& P);
-void bn_null_vectors(const PlanData& P, const double* Om, int64_t s, double* Pall);
 
 // Operators.
 enum class OpType { Dense, Kernel, Callback };

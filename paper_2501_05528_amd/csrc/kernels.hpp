@@ -106,6 +106,12 @@ void launch_expand_masked(const PlanData& P, const DeviceTables& t, const double
 void launch_take_box_rows(const PlanData& P, const DeviceTables& t, const double* Yc, int i0, int i1,
                           double* S, hipStream_t s);
 // Alg. 1: S(row, :) = Y(row, :) P_box(row) with Y N x ns and P b blocks of ns x r.
+// Alg. 1 null vectors on the device: P (b blocks of ns x r) from the N x ns test matrix;
+// work holds bn_null_workspace_doubles(P, ns) doubles; flag[0] = 1 on a rank-deficient
+// neighbour block (the caller zeroes it first).
+int64_t bn_null_workspace_doubles(const PlanData& P, int64_t ns);
+void launch_bn_null(const PlanData& P, const DeviceTables& t, const double* Om, int64_t ns, double* work,
+                    double* Pall, double* flag, hipStream_t s);
 void launch_bn_project(const PlanData& P, const DeviceTables& t, const double* Y, int64_t ns,
                        const double* Pall, double* S, hipStream_t s);
 void launch_identity_probe(const PlanData& P, const DeviceTables& t, int c, double* X, hipStream_t s);

@@ -6,6 +6,7 @@ caller's products (Python callback running a dense product on the library's stre
 * Results against the oracle (same tolerances as tests/test_gpu_parity.py): the
   sketches to 1e-12, every far block U_i Atil_ij V_j* and near block plus B_ij to
   1e-11 max|A|, and the power estimate of ||A - A_uBLR||_2 in the 1.5 band.
+* A failing product ends the call with BLR_ERR_OPERATOR.
 * The exact Frobenius error, which needs entry access, is refused with BLR_ERR_UNSUPPORTED
   (the mixed-precision modes through a black box are tested in test_gpu_blackbox_mixed.py).
 * The host export returns the same arrays as the device parts.
@@ -132,3 +133,38 @@ def test_export_matches_parts(run):
         dev = h.part(name).cpu().numpy()
         host = h.export(name)
         assert np.array_equal(host, dev.reshape(-1, order="F"))
+
+
+def test_operator_failure_reported():
+    """A caller's product that fails (nonzero return) ends the call with BLR_ERR_OPERATOR
+    and no handle; the same for the low-precision products of the mixed modes."""
+    import torch
+    import paper_2501_05528_amd as P
+    g, A, k, p, seed = _case("log_ragged")
+    near = O.near_lists(g.lattice)
+    T = W.tag_matrix(seed, g.nboxes, O.num_tag_columns(near, 3))
+    G, H = (P.colmajor(a) for a in W.gaussian_test_blocks(seed, g.n, k + p))
+    plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
+    Ad = torch.as_tensor(A, device="cuda")
+    calls = {"n": 0}
+
+    def flaky(X, trans):
+        calls["n"] += 1
+        if calls["n"] >= 2:
+            raise RuntimeError("planted operator failure")
+        return (Ad.t().contiguous() if trans else Ad) @ X
+
+    op = P.Operator.from_matmat(g.n, flaky)
+    with pytest.raises(P.BlrError) as ei:
+        P.compress(plan, op, G, H)
+    assert ei.value.name == "BLR_ERR_OPERATOR"
+    assert calls["n"] == 2                     # the failing call ends the compression
+
+    def bad_lp(X, trans, precision):
+        raise RuntimeError("planted low-precision failure")
+
+    op2 = P.Operator.from_matmat(g.n, lambda X, trans: (Ad.t().contiguous() if trans else Ad) @ X, bad_lp)
+    gam = torch.as_tensor(W.refinement_gammas(seed, g.nboxes, k + p, k + p)[0], device="cuda")
+    with pytest.raises(P.BlrError) as ei:
+        P.compress(plan, op2, G, H, precision="bf16", gamma_u=gam, gamma_v=gam)
+    assert ei.value.name == "BLR_ERR_OPERATOR"

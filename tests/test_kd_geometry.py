@@ -55,3 +55,18 @@ def test_plan_on_kd_lists_matches_oracle():
     zo, rhoo = O.tag_plan(T, near, far)
     assert np.allclose(rho, rhoo, rtol=1e-9, atol=0)
     assert np.allclose(z, zo, rtol=0, atol=1e-9)
+
+
+def test_any_box_count():
+    """With nboxes given, the tessellation has exactly that many boxes of n / nboxes points
+    up to one, cells that tile the square, and every point inside its box's cell."""
+    for n, b in ((2000, 77), (1500, 10), (777, 1)):
+        g, near, cells = W.kd_geometry(n, 2, 0, 5, nboxes=b)
+        sizes = g.box_sizes()
+        assert g.nboxes == b and sizes.sum() == n
+        assert sizes.max() - sizes.min() <= 1
+        assert np.isclose(np.prod(cells[:, :, 1] - cells[:, :, 0], axis=1).sum(), 1.0)
+        for i in range(b):
+            p = g.pts[g.box_ptr[i]:g.box_ptr[i + 1]]
+            assert np.all((p >= cells[i, :, 0]) & (p <= cells[i, :, 1]))
+            assert i in near[i]

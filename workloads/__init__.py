@@ -313,7 +313,7 @@ def irregular_grid_geometry(widths_per_axis, jitter: float = 0.0, seed: int = 0)
 STREAM_POINTS = 10
 
 
-def kd_geometry(n: int, dim: int, levels: int, seed: int):
+def kd_geometry(n: int, dim: int, levels: int, seed: int, nboxes: int = 0):
     """Uniformly random points in [0,1]^dim tessellated by median splits.
 
     The unit cube is halved ``levels`` times, cycling through the axes; each cut
@@ -321,6 +321,10 @@ def kd_geometry(n: int, dim: int, levels: int, seed: int):
     the 2^levels boxes hold n / 2^levels points each, up to one (the geometry of
     Section 7: the domain is subdivided until every box reaches the desired
     cardinality).  Boxes are numbered in tree order and rows are box-major.
+    With ``nboxes`` > 0 the count need not be a power of two: a cell that is to
+    hold c boxes is cut, along the axis of its depth, into cells for c // 2 and
+    c - c // 2 boxes, at the point rank n_cell (c // 2) / c, so every box holds
+    n / nboxes points up to one (``levels`` is then ignored).
 
     Returns (Geometry with ``lattice`` None, near lists, cells) where ``cells``
     is (b, dim, 2) with the closed [lo, hi] range of every box per axis and
@@ -328,19 +332,27 @@ def kd_geometry(n: int, dim: int, levels: int, seed: int):
     with box i's (box i included, Section 2.5).
     """
     pts0 = rng(seed, STREAM_POINTS).uniform(0.0, 1.0, size=(n, dim))
-    boxes = [(np.arange(n), np.array([[0.0, 1.0]] * dim))]
-    for lev in range(levels):
-        ax = lev % dim
+    target = nboxes if nboxes > 0 else 2 ** levels
+    boxes = [(np.arange(n), np.array([[0.0, 1.0]] * dim), target)]
+    depth = 0
+    while any(c > 1 for _, _, c in boxes):
+        ax = depth % dim
         nxt = []
-        for idx, cell in boxes:
+        for idx, cell, c in boxes:
+            if c == 1:
+                nxt.append((idx, cell, c))
+                continue
             order = idx[np.argsort(pts0[idx, ax], kind="stable")]
-            h = len(order) // 2
+            c_lo = c // 2
+            h = (len(order) * c_lo) // c
             cut = 0.5 * (pts0[order[h - 1], ax] + pts0[order[h], ax])
             lo_cell, hi_cell = cell.copy(), cell.copy()
             lo_cell[ax, 1] = cut
             hi_cell[ax, 0] = cut
-            nxt += [(order[:h], lo_cell), (order[h:], hi_cell)]
+            nxt += [(order[:h], lo_cell, c_lo), (order[h:], hi_cell, c - c_lo)]
         boxes = nxt
+        depth += 1
+    boxes = [(idx, cell) for idx, cell, _ in boxes]
     pts = np.concatenate([pts0[idx] for idx, _ in boxes], axis=0)
     box_ptr = np.concatenate([[0], np.cumsum([len(idx) for idx, _ in boxes])]).astype(np.int64)
     cells = np.stack([cell for _, cell in boxes])
