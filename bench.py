@@ -513,7 +513,9 @@ def _kw(j):
 def batch_section(njobs=96, seed=20250104, n_lo=4096, n_hi=65536):
     """Uneven batch (the batch generator: N, box shape, rank, kernel per job): FP32-sketch
     mixed jobs in one batch (persistent sketch launches, HIP graph replay, autotuned
-    tiles) against plain FP64 compressions one at a time, with the accuracy of each."""
+    tiles) against plain FP64 compressions one at a time, with the accuracy of each; and
+    the FP64 jobs as one batch (persistent FP64 sketch launches, one eager run), which
+    separates the batching gain from the precision gain."""
     import torch
     import paper_2501_05528_amd as P
     torch.cuda.empty_cache()
@@ -530,6 +532,15 @@ def batch_section(njobs=96, seed=20250104, n_lo=4096, n_hi=65536):
     t64 = time.perf_counter() - t0
     e64 = [h.error_fro(j["op"]) for h, j in zip(hs64, jobs64)]
     del hs64
+    # the same FP64 jobs as one batch: persistent FP64 sketch launches (one per kernel kind
+    # and column-tile class), one eager run
+    b64 = P.Batch(jobs64, graph=False, autotune=False)
+    rep64 = b64.run()
+    torch.cuda.synchronize()
+    e64b = max(abs(b64.result(q).error_fro(j["op"]) - e) / e for q, (j, e) in
+               enumerate(zip(jobs64[:4], e64[:4])))
+    del b64
+    torch.cuda.empty_cache()
     b = P.Batch(jobs32, graph=True, autotune=True)
     rep_eager = b.run()
     b.run()
@@ -547,6 +558,12 @@ def batch_section(njobs=96, seed=20250104, n_lo=4096, n_hi=65536):
             "note": "N up to 65536: with N up to 131072 the 96 jobs' outputs and temporaries, which a "
                     "batch keeps resident, need about 570 GB",
             "fp64_one_at_a_time_jobs_per_s": round(njobs / t64, 3),
+            "batched_fp64_jobs_per_s": round(njobs / (rep64["ms_total"] * 1e-3), 3),
+            "batched_fp64_sketch_ms": round(rep64["ms_sketch"], 3),
+            "batched_fp64_sketch_tflops": round(rep64["sketch_flops"] / (rep64["ms_sketch"] * 1e-3) / 1e12, 2),
+            "batched_fp64_classes": {"ntr": rep64["class_ntr"], "kind": rep64["class_kind"],
+                                     "jobs": rep64["class_jobs"]},
+            "batched_fp64_err_rel_diff_first4": e64b,
             "batched_fp32_jobs_per_s": round(njobs / tb, 3),
             "speedup": round(t64 / tb, 3),
             "max_err_ratio_vs_fp64": round(ratio, 4),

@@ -598,26 +598,34 @@ enum {
                                  sketch per class and keep the fastest (cached per device) */
 };
 
+#define BLR_BATCH_MAX_CLASSES 32
+
 typedef struct blr_batch_report {
     double ms_total;          /* the batch on the device (events on the batch stream) */
-    double ms_sketch;         /* the low-precision sketch launches (0 when a graph is replayed) */
+    double ms_sketch;         /* the persistent sketch launches (0 when a graph is replayed) */
     double sketch_flops;      /* sum over jobs of 4 N^2 ell r_lo (4 N^2 ell r for FP64 jobs) */
     double refine_flops;      /* sum over mixed jobs of the refinement's far-field flops */
     int64_t applies;          /* sum over jobs of the products in the paper's convention */
     int32_t graph_replayed;   /* 1 if this run replayed the captured graph */
-    int32_t nclasses;         /* persistent sketch launches (one per precision and column tiles) */
-    int32_t class_precision[8], class_ntr[8], class_spw[8], class_jobs[8];
+    int32_t nclasses;         /* persistent sketch launches: one per (precision, 16-column tiles)
+                                 and, for FP64, per kernel kind */
+    int32_t class_precision[BLR_BATCH_MAX_CLASSES], class_ntr[BLR_BATCH_MAX_CLASSES];
+    int32_t class_spw[BLR_BATCH_MAX_CLASSES];   /* tag columns per wave of the launch */
+    int32_t class_jobs[BLR_BATCH_MAX_CLASSES];
+    int32_t class_kind[BLR_BATCH_MAX_CLASSES];  /* blr_kernel_kind of an FP64 class, -1 otherwise */
 } blr_batch_report;
 
 /*
  * Plans the batch and allocates every output and temporary up front (no device
- * allocation happens in blr_batch_run).  Mixed-precision kernel-matrix jobs share
- * persistent sketch launches, one per (precision, 16-column tiles of r_lo) class,
- * whose workgroups stride over (job, 32-row block, tag column group) items,
- * heaviest first; every other stage runs per job.  Jobs on dense operators and
- * FP64 jobs use the single-job sketch kernels.  Black-box (callback) operators
- * are not supported (BLR_ERR_UNSUPPORTED).  flags: BLR_BATCH_GRAPH,
- * BLR_BATCH_AUTOTUNE.
+ * allocation happens in blr_batch_run).  Kernel-matrix jobs share persistent sketch
+ * launches whose workgroups stride over (job, row block, tag column group) items,
+ * heaviest job first: mixed-precision jobs one launch per (precision, 16-column
+ * tiles of r_lo) class (32-row blocks, every kernel kind in one launch), FP64 jobs
+ * one per (16-column tiles of r, kernel kind) class (8-row blocks).  At most
+ * BLR_BATCH_MAX_CLASSES classes (else BLR_ERR_UNSUPPORTED).  Every other stage runs
+ * per job; jobs on dense operators use the single-job sketch kernels.  Black-box
+ * (callback) operators are not supported (BLR_ERR_UNSUPPORTED).  flags:
+ * BLR_BATCH_GRAPH, BLR_BATCH_AUTOTUNE (low-precision classes only).
  */
 blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t flags, blr_batch** out);
 

@@ -49,6 +49,7 @@ class Report(ctypes.Structure):
 
 
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+BATCH_MAX_CLASSES = 32   # BLR_BATCH_MAX_CLASSES
 
 
 class BatchJob(ctypes.Structure):
@@ -59,8 +60,9 @@ class BatchJob(ctypes.Structure):
 class BatchReport(ctypes.Structure):
     _fields_ = [("ms_total", c_double), ("ms_sketch", c_double), ("sketch_flops", c_double),
                 ("refine_flops", c_double), ("applies", c_int64), ("graph_replayed", c_int32),
-                ("nclasses", c_int32), ("class_precision", c_int32 * 8), ("class_ntr", c_int32 * 8),
-                ("class_spw", c_int32 * 8), ("class_jobs", c_int32 * 8)]
+                ("nclasses", c_int32), ("class_precision", c_int32 * BATCH_MAX_CLASSES),
+                ("class_ntr", c_int32 * BATCH_MAX_CLASSES), ("class_spw", c_int32 * BATCH_MAX_CLASSES),
+                ("class_jobs", c_int32 * BATCH_MAX_CLASSES), ("class_kind", c_int32 * BATCH_MAX_CLASSES)]
 
 
 class ServerJobStats(ctypes.Structure):

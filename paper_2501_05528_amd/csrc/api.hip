@@ -1563,8 +1563,10 @@ struct BatchJob {
 
 struct SketchClass {
     int precision = 0, ntr = 0;
+    int kind = -1;                 // FP64 classes: the kernel kind of every member
     std::vector<int> members;
     LpJob* d_jobs = nullptr;
+    Fp64Job* d_jobs64 = nullptr;
     int nspw = 0;
     int spw[2] = {0, 0};
     int4* d_items[2] = {nullptr, nullptr};
@@ -1626,13 +1628,17 @@ void batch_enqueue(blr_batch& B, bool time_sketch) {
             launch_pack_lp(P, *j.t, j.precision, j.r_lo, j.H, j.PH, s);
             if (!j.persistent) launch_sketch_lp(*j.op, P, *j.t, j.precision, j.r_lo, j.PG, j.PH, j.Y0, j.Z0, s);
         } else {
-            launch_sketch(*j.op, P, *j.t, j.G, j.H, j.Y, j.Z, s);
+            if (!j.persistent) launch_sketch(*j.op, P, *j.t, j.G, j.H, j.Y, j.Z, s);
         }
     }
     if (time_sketch) HIPC(hipEventRecord(B.e0, s));
-    for (auto& c : B.classes)
-        launch_sketch_lp_multi(c.precision, c.ntr, c.spw[c.chosen], c.d_jobs, c.d_items[c.chosen],
-                               c.nitems[c.chosen], B.grid, s);
+    for (auto& c : B.classes) {
+        if (c.precision == BLR_PREC_FP64)
+            launch_sketch_multi(c.kind, c.ntr, c.spw[0], c.d_jobs64, c.d_items[0], c.nitems[0], B.grid, s);
+        else
+            launch_sketch_lp_multi(c.precision, c.ntr, c.spw[c.chosen], c.d_jobs, c.d_items[c.chosen],
+                                   c.nitems[c.chosen], B.grid, s);
+    }
     if (time_sketch) HIPC(hipEventRecord(B.e1, s));
     for (auto& j : B.jobs) {
         const PlanData& P = *j.plan;
@@ -1662,6 +1668,7 @@ void batch_enqueue(blr_batch& B, bool time_sketch) {
 void batch_autotune(blr_batch& B) {
     hipStream_t s = B.own;
     for (auto& c : B.classes) {
+        if (c.precision == BLR_PREC_FP64) continue;  // one tile shape per FP64 class
         const auto key = std::make_tuple(B.device, c.precision, c.ntr);
         {
             std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -1763,29 +1770,92 @@ blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t fl
             } else {
                 j.Y = B->alloc<double>(P.n * LR);
                 j.Z = B->alloc<double>(P.n * LR);
+                j.persistent = o.type == OpType::Kernel;
             }
             j.Yh = B->alloc<double>(P.n * j.r_lo);
             j.Zh = B->alloc<double>(P.n * j.r_lo);
             j.nfw = B->alloc<double>(nearfield_workspace_doubles(P));
         }
-        // persistent sketch classes: (precision, column tiles)
+        // persistent sketch classes: (precision, column tiles), FP64 also by kernel kind
         for (int q = 0; q < njobs; ++q) {
             BatchJob& j = B->jobs[q];
             if (!j.persistent) continue;
             const int ntr = (j.r_lo + 15) / 16;
+            const int kind = j.precision == BLR_PREC_FP64 ? j.op->kind : -1;
             SketchClass* c = nullptr;
             for (auto& x : B->classes)
-                if (x.precision == j.precision && x.ntr == ntr) c = &x;
+                if (x.precision == j.precision && x.ntr == ntr && x.kind == kind) c = &x;
             if (!c) {
-                if (B->classes.size() >= 8) fail(BLR_ERR_UNSUPPORTED, "more than 8 sketch classes");
+                if (B->classes.size() >= BLR_BATCH_MAX_CLASSES) fail(BLR_ERR_UNSUPPORTED, "too many sketch classes");
                 B->classes.emplace_back();
                 c = &B->classes.back();
                 c->precision = j.precision;
                 c->ntr = ntr;
+                c->kind = kind;
             }
             c->members.push_back(q);
         }
         for (auto& c : B->classes) {
+            if (c.precision != BLR_PREC_FP64) continue;
+            // tag columns per wave: the fewest of {max, max - 1} that hold every member's
+            // groups (ceil(ell / (4 max)) groups, split evenly)
+            const int svw_max = fp64_sketch_svw(c.ntr);
+            auto groups_of = [&](const PlanData& P) { return (P.ell + 4 * svw_max - 1) / (4 * svw_max); };
+            int need = 1;
+            for (int q : c.members) {
+                const PlanData& P = *B->jobs[q].plan;
+                const int ng = groups_of(P);
+                need = std::max(need, ((P.ell + ng - 1) / ng + 3) / 4);
+            }
+            c.nspw = 1;
+            c.spw[0] = (svw_max > 1 && need <= svw_max - 1) ? svw_max - 1 : svw_max;
+            std::vector<Fp64Job> fj;
+            for (int q : c.members) {
+                const BatchJob& j = B->jobs[q];
+                const PlanData& P = *j.plan;
+                Fp64Job d{};
+                d.kind = j.op->kind;
+                d.diag = j.op->kind == BLR_KERNEL_EXP ? 1.0 : (j.op->kind == BLR_KERNEL_COS ? 1000.0 : 0.0);
+                d.px = j.op->pts;
+                d.py = j.op->pts + P.n;
+                d.pz = j.op->pts + 2 * P.n;
+                d.T = j.t->T;
+                d.box_ptr = j.t->box_ptr;
+                d.nbox = P.b;
+                d.r = P.r;
+                d.ell = P.ell;
+                d.n = P.n;
+                d.G0 = j.G;
+                d.G1 = j.H;
+                d.Y0 = j.Y;
+                d.Y1 = j.Z;
+                d.ngroups = groups_of(P);
+                fj.push_back(d);
+            }
+            c.d_jobs64 = B->alloc<Fp64Job>(static_cast<int64_t>(fj.size()));
+            HIPC(hipMemcpy(c.d_jobs64, fj.data(), fj.size() * sizeof(Fp64Job), hipMemcpyHostToDevice));
+            // items: (job index in class, 8-row block, tag column group), heaviest job first
+            std::vector<std::pair<double, int4>> items;
+            for (size_t u = 0; u < c.members.size(); ++u) {
+                const PlanData& P = *B->jobs[c.members[u]].plan;
+                const int groups = groups_of(P);
+                const int64_t blocks = (P.n + 7) / 8;
+                if (blocks > INT32_MAX) fail(BLR_ERR_UNSUPPORTED, "job too large for the batch");
+                const double cost = static_cast<double>(P.n) * P.ell;
+                for (int64_t rb = 0; rb < blocks; ++rb)
+                    for (int g = 0; g < groups; ++g)
+                        items.push_back({cost, int4{static_cast<int>(u), static_cast<int>(rb), g, 0}});
+            }
+            std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+            std::vector<int4> flat(items.size());
+            for (size_t u = 0; u < items.size(); ++u) flat[u] = items[u].second;
+            if (flat.size() > static_cast<size_t>(INT32_MAX)) fail(BLR_ERR_UNSUPPORTED, "batch too large");
+            c.d_items[0] = B->alloc<int4>(static_cast<int64_t>(flat.size()));
+            HIPC(hipMemcpy(c.d_items[0], flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice));
+            c.nitems[0] = static_cast<int>(flat.size());
+        }
+        for (auto& c : B->classes) {
+            if (c.precision == BLR_PREC_FP64) continue;
             std::vector<LpJob> lj;
             for (int q : c.members) {
                 const BatchJob& j = B->jobs[q];
@@ -1913,6 +1983,7 @@ blr_status blr_batch_run(blr_batch* b, void* stream, blr_batch_report* rep) {
             rep->nclasses = static_cast<int32_t>(b->classes.size());
             for (size_t q = 0; q < b->classes.size(); ++q) {
                 rep->class_precision[q] = b->classes[q].precision;
+                rep->class_kind[q] = b->classes[q].kind;
                 rep->class_ntr[q] = b->classes[q].ntr;
                 rep->class_spw[q] = b->classes[q].spw[b->classes[q].chosen];
                 rep->class_jobs[q] = static_cast<int32_t>(b->classes[q].members.size());

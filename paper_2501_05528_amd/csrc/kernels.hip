@@ -88,6 +88,13 @@ __device__ inline double log_pos(double x) {
 }
 
 #define BLR_LDS __attribute__((address_space(3)))
+#define BLR_GLB __attribute__((address_space(1)))
+// A pointer from a job descriptor in memory, marked as device global memory so
+// that accesses through it compile to global (not flat) instructions.
+template <class T>
+__device__ inline BLR_GLB T* as_glb(T* p) {
+    return (BLR_GLB T*)p;
+}
 
 // Table-driven natural logarithm for the kernel-matrix entries.  x = m 2^e with
 // m in [1/sqrt2, sqrt2); the top six mantissa bits of m (and its binade) pick one
@@ -425,30 +432,32 @@ __device__ inline double mfma44(double a, double b, double c) {
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <class AS, int NTR, int NSIDE, int SVW, int KT>
-__global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restrict__ T,
-                                                    const int64_t* __restrict__ box_ptr, int nbox,
-                                                    const double* __restrict__ G0,
-                                                    const double* __restrict__ G1, int64_t n,
-                                                    int r, int ell, double* __restrict__ Y0,
-                                                    double* __restrict__ Y1) {
-    __shared__ __attribute__((aligned(16))) double s_ltab[256];
-    A.prepare((BLR_LDS double*)s_ltab);
-    __syncthreads();
+// One workgroup tile of the sketch: target rows [BM rt_blk, BM rt_blk + BM) and tag
+// column group grp of ngroups.  The split of the tag columns over groups and waves does
+// not change any column's arithmetic.  sAp / sBp: the double-buffered LDS tiles (2 x KT*BM and
+// 2 x (KT+1)*BW doubles).
+template <class AS, int NTR, int NSIDE, int SVW, int KT, bool EVEN>
+__device__ __attribute__((always_inline)) inline void sketch_tile(
+    const AS& A, const double* __restrict__ T, const int64_t* __restrict__ box_ptr, int nbox,
+    const double* __restrict__ G0, const double* __restrict__ G1, int64_t n, int r, int ell,
+    double* __restrict__ Y0, double* __restrict__ Y1, int64_t rt_blk, int grp, int ngroups,
+    BLR_LDS double* sAp, BLR_LDS double* sBp, int tid) {
     constexpr int MA = 2, BM = 4 * MA, CW = NTR * 16;            // rows, cols/side (KT sources/step)
     constexpr int BW = NSIDE * CW;                               // B tile width
     constexpr int BPT = (KT * BW + 255) / 256;
     constexpr int AGEN = BM * KT;                                // A tile entries per step
     static_assert(AGEN <= 256, "tile shape");
-    __shared__ double sA[2][KT * BM];
     constexpr int KTP = KT + 1;                  // padded column stride of the B tile
-    __shared__ double sB[2][KTP * BW];
-    const int tid = threadIdx.x, lane = tid & 63;
+    BLR_LDS double (*sA)[KT * BM] = reinterpret_cast<BLR_LDS double (*)[KT * BM]>(sAp);
+    BLR_LDS double (*sB)[KTP * BW] = reinterpret_cast<BLR_LDS double (*)[KTP * BW]>(sBp);
+    const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BM;
-    // this wave's tag columns: a balanced contiguous chunk of the group's
-    const int sg0 = blockIdx.y * 4 * SVW;
-    const int sgn = min(4 * SVW, ell - sg0);
+    const int64_t row0 = rt_blk * BM;
+    // this wave's tag columns: a balanced contiguous chunk of the group's.  Groups: 4 SVW
+    // tag columns each (the last one the rest), or with EVEN the ell columns split evenly
+    // over ngroups >= ell / (4 SVW) groups
+    const int sg0 = EVEN ? (grp * ell) / ngroups : grp * 4 * SVW;
+    const int sgn = EVEN ? ((grp + 1) * ell) / ngroups - sg0 : min(4 * SVW, ell - sg0);
     const int s_lo = sg0 + (wave * sgn) / 4;
     const int nsv = sg0 + ((wave + 1) * sgn) / 4 - s_lo;
     // A generation: threads t < AGEN own entry (row t % BM, kk = t / BM)
@@ -595,6 +604,59 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     }
 }
 
+template <class AS, int NTR, int NSIDE, int SVW, int KT>
+__global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restrict__ T,
+                                                    const int64_t* __restrict__ box_ptr, int nbox,
+                                                    const double* __restrict__ G0,
+                                                    const double* __restrict__ G1, int64_t n,
+                                                    int r, int ell, double* __restrict__ Y0,
+                                                    double* __restrict__ Y1) {
+    constexpr int BM = 8, BW = NSIDE * NTR * 16;
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    __shared__ double sA[2 * KT * BM];
+    __shared__ double sB[2 * (KT + 1) * BW];
+    A.prepare((BLR_LDS double*)s_ltab);
+    __syncthreads();
+    sketch_tile<AS, NTR, NSIDE, SVW, KT, false>(A, T, box_ptr, nbox, G0, G1, n, r, ell, Y0, Y1, blockIdx.x,
+                                                blockIdx.y, gridDim.y, (BLR_LDS double*)sA, (BLR_LDS double*)sB,
+                                                static_cast<int>(threadIdx.x));
+}
+
+// Persistent form over a batch of FP64 kernel-matrix jobs of one kernel kind (both
+// sides): workgroups stride over a list of (job, 8-row block, tag column group) items,
+// heaviest job first.  One kind per launch: a per-entry switch over the kinds makes the
+// FP64 exp and cos paths spill registers.  The tag columns are split evenly over the
+// groups, so a class can use one tag column per wave fewer than k_sketch when every job
+// allows it (for ell = 13 and 4 column tiles: 2 groups of 6 and 7 instead of 12 and 1, and
+// no spills).  Each tag column's sums run in the same order as in k_sketch, so a job's Y
+// and Z equal its single-job sketch bit for bit.
+template <int KIND, int NTR, int SVW>
+__global__ __launch_bounds__(256, 2) void k_sketch_multi(const Fp64Job* __restrict__ jobs,
+                                                         const int4* __restrict__ items, int nitems) {
+    constexpr int KT = 32, BM = 8, BW = 2 * NTR * 16;
+    __shared__ __attribute__((aligned(16))) double s_ltab[256];
+    __shared__ double sA[2 * KT * BM];
+    __shared__ double sB[2 * (KT + 1) * BW];
+    KernelSrc<KIND> A{nullptr, nullptr, nullptr, 0.0};
+    A.prepare((BLR_LDS double*)s_ltab);
+    BLR_LDS double* lA = (BLR_LDS double*)sA;
+    BLR_LDS double* lB = (BLR_LDS double*)sB;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        const Fp64Job& J = jobs[w.x];
+        A.px = (const double*)as_glb(J.px);
+        A.py = (const double*)as_glb(J.py);
+        A.pz = (const double*)as_glb(J.pz);
+        A.diag = J.diag;
+        __syncthreads();  // the table is built; the previous item's last reads of LDS are done
+        sketch_tile<KernelSrc<KIND>, NTR, 2, SVW, KT, true>(
+            A, (const double*)as_glb(J.T), (const int64_t*)as_glb(J.box_ptr), J.nbox,
+            (const double*)as_glb(J.G0), (const double*)as_glb(J.G1), J.n, J.r, J.ell,
+            (double*)as_glb(J.Y0), (double*)as_glb(J.Y1), w.y, w.z, J.ngroups, lA, lB,
+            static_cast<int>(threadIdx.x));
+    }
+}
+
 template <class AS>
 void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double* G0,
                    const double* G1, int nside, double* Y0, double* Y1, hipStream_t s) {
@@ -629,6 +691,43 @@ void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double*
 #undef BLR_SKETCH_CASE
     check_launch("tagged sketch");
 }
+
+}  // namespace
+
+int fp64_sketch_svw(int ntr) { return std::max(1, std::min(8, 12 / std::max(1, ntr))); }
+
+void launch_sketch_multi(int kind, int ntr, int svw, const Fp64Job* jobs, const int4* items, int nitems,
+                         int grid, hipStream_t s) {
+    if (nitems <= 0) return;
+    const dim3 g(static_cast<unsigned>(std::max(1, std::min(grid, nitems))));
+    auto run = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        // SVW: fp64_sketch_svw(ntr) or one less
+#define BLR_MULTI(NTRV, SVWV) hipLaunchKernelGGL((k_sketch_multi<K, NTRV, SVWV>), g, dim3(256), 0, s, jobs, items, nitems)
+        if (ntr == 1 && svw == 8) BLR_MULTI(1, 8);
+        else if (ntr == 1 && svw == 7) BLR_MULTI(1, 7);
+        else if (ntr == 2 && svw == 6) BLR_MULTI(2, 6);
+        else if (ntr == 2 && svw == 5) BLR_MULTI(2, 5);
+        else if (ntr == 3 && svw == 4) BLR_MULTI(3, 4);
+        else if (ntr == 3 && svw == 3) BLR_MULTI(3, 3);
+        else if (ntr == 4 && svw == 3) BLR_MULTI(4, 3);
+        else if (ntr == 4 && svw == 2) BLR_MULTI(4, 2);
+        else if (ntr == 5 && svw == 2) BLR_MULTI(5, 2);
+        else if (ntr == 5 && svw == 1) BLR_MULTI(5, 1);
+        else fail(BLR_ERR_UNSUPPORTED, "no persistent FP64 sketch for this column-tile count and SVW");
+#undef BLR_MULTI
+    };
+    switch (kind) {
+        case BLR_KERNEL_LOG: run(std::integral_constant<int, BLR_KERNEL_LOG>{}); break;
+        case BLR_KERNEL_INV_R: run(std::integral_constant<int, BLR_KERNEL_INV_R>{}); break;
+        case BLR_KERNEL_EXP: run(std::integral_constant<int, BLR_KERNEL_EXP>{}); break;
+        case BLR_KERNEL_COS: run(std::integral_constant<int, BLR_KERNEL_COS>{}); break;
+        default: fail(BLR_ERR_INVALID_ARG, "unknown kernel kind");
+    }
+    check_launch("persistent tagged sketch");
+}
+
+namespace {
 
 // Calls f(src) with the entry source of the operator (or of its adjoint).
 template <class F>

@@ -56,6 +56,33 @@ struct LpJob {
     float* Y0;                // N x ell r_lo
     float* Y1;
 };
+// One kernel-matrix job of a persistent FP64 sketch launch (device array).
+struct Fp64Job {
+    int kind;                 // blr_kernel_kind (the same for every job of a launch)
+    double diag;              // kernel diagonal value
+    const double* px;         // FP64 points, SoA
+    const double* py;
+    const double* pz;
+    const double* T;          // b x ell row-major
+    const int64_t* box_ptr;   // [b+1]
+    int nbox;
+    int r;
+    int ell;
+    int64_t n;
+    const double* G0;         // N x r
+    const double* G1;
+    double* Y0;               // N x ell r
+    double* Y1;
+    int ngroups;              // tag column groups (items carry the group index)
+};
+// Most tag columns per wave of the FP64 sketch for r = 16 ntr columns per side, both
+// sides (the single-job choice); a workgroup covers 4 of them per group.
+int fp64_sketch_svw(int ntr);
+// Persistent FP64 sketch over items (job, 8-row block, tag column group) of jobs of
+// one kernel kind; svw is fp64_sketch_svw(ntr) or one less, and every job's groups
+// hold at most 4 svw tag columns.  Grid workgroups stride over the items.
+void launch_sketch_multi(int kind, int ntr, int svw, const Fp64Job* jobs, const int4* items, int nitems,
+                         int grid, hipStream_t s);
 // Tag columns per wave (SPW) offered to the autotuner for a (precision, column
 // tiles) class; a workgroup covers 2 SPW tag columns.  Returns the count (<= 2).
 int lp_multi_spw_candidates(int precision, int ntr, int* spw);

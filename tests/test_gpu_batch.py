@@ -5,7 +5,8 @@ operator among them.
 * Every job's U, V, Atil, B from the batch equal those of blr_tag_compress on the same
   inputs, bit for bit, on the eager first run, on the run that captures the HIP graph and
   on later replays (with unrelated eager work on the stream between replays).
-* The autotuner picks one of the offered tile shapes per persistent sketch class.
+* The autotuner picks one of the offered tile shapes per persistent sketch class; every
+  kernel-matrix job, FP64 ones included, sketches in a persistent class launch.
 * A sampled job's error meets the 1.5 band of the FP64 oracle's plain tagging.
 """
 import numpy as np
@@ -17,7 +18,9 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 SPW_CANDIDATES = {2: {1: (8, 4), 2: (8, 4), 3: (6, 4), 4: (4, 3), 5: (3, 2)},
-                  1: {1: (8, 4), 2: (7, 4), 3: (4, 3), 4: (3, 2), 5: (2, 1)}}
+                  1: {1: (8, 4), 2: (7, 4), 3: (4, 3), 4: (3, 2), 5: (2, 1)},
+                  0: {1: (8, 7), 2: (6, 5), 3: (4, 3), 4: (3, 2), 5: (2, 1)}}   # FP64: as many as the jobs need
+KIND_CODE = {"log": 0, "inv_r": 1, "exp": 2, "cos": 3}
 
 
 def _announce(msg):
@@ -104,6 +107,14 @@ def test_batch_equals_single_jobs_eager_and_graph(batch_setup):
         _check_equal(b, singles)
     for prec, ntr, spw in zip(rep2["class_precision"], rep2["class_ntr"], rep2["class_spw"]):
         assert spw in SPW_CANDIDATES[prec][ntr]
+    # every kernel-matrix job sketches in a persistent launch: FP64 jobs in classes of one
+    # kernel kind and column-tile count
+    fp64 = [sp for sp in specs if sp["precision"] == "fp64" and "A" not in sp]
+    assert sum(nj for prec, nj in zip(rep2["class_precision"], rep2["class_jobs"]) if prec == 0) == len(fp64)
+    want = sorted({(KIND_CODE[sp["wl"].kind], (sp["wl"].k + sp["wl"].p + 15) // 16) for sp in fp64})
+    got = sorted((kd, ntr) for prec, kd, ntr in zip(rep2["class_precision"], rep2["class_kind"],
+                                                    rep2["class_ntr"]) if prec == 0)
+    assert got == want, (got, want)
     assert rep2["sketch_flops"] > 0 and rep2["applies"] > 0
 
 
