@@ -196,8 +196,9 @@ typedef int32_t (*blr_apply_fn)(void* ctx, int32_t trans, int64_t ncols, const d
  * optional FP32-operand products (blr_op_callback_set_lp), else the FP64
  * products rounded to FP32; the refinement sketch applies A and A* to
  * block-diagonal test columns (b r per side, in chunks of boxes) and sums each
- * row box's far blocks.  blr_error_fro and batches, which need entry access,
- * return BLR_ERR_UNSUPPORTED for such operators.
+ * row box's far blocks.  blr_error_fro takes the entries from N products with
+ * unit columns.  Batches need entry access and return BLR_ERR_UNSUPPORTED for
+ * such operators.
  */
 blr_status blr_op_callback_create(int64_t n, blr_apply_fn apply, void* ctx, blr_operator** out);
 
@@ -225,8 +226,8 @@ blr_status blr_op_callback_set_lp(blr_operator* op, blr_apply_lp_fn apply_lp);
  * `row` (a permutation; copied).  Products use the separable exact solve: sine
  * transforms in the plane and one tridiagonal z-line pivot per mode pair.
  * Errors: n < 1, l < 1, bad perm, or an internal block that is not positive
- * definite (a resonant slab) give BLR_ERR_INVALID_ARG.  Entry-based calls
- * (blr_error_fro, mixed precision, batches) return BLR_ERR_UNSUPPORTED.
+ * definite (a resonant slab) give BLR_ERR_INVALID_ARG.  Every call that takes a
+ * callback operator takes this one (batches return BLR_ERR_UNSUPPORTED).
  */
 blr_status blr_op_slab_create(int32_t n, int32_t l, double kappa_h, const int64_t* perm, blr_operator** out);
 void blr_op_destroy(blr_operator* op);
@@ -554,9 +555,12 @@ blr_status blr_apply_noalloc(const blr_ublr* h, int32_t trans, int64_t ncols, co
                              int64_t ldx, double* y, int64_t ldy, void* stream);
 
 /*
- * Exact relative Frobenius error ||A - A_uBLR||_F / ||A||_F of a built-in
- * operator, block by block with entry access (evaluation harness; not part
- * of the black-box method).  Synchronises the stream.
+ * Exact relative Frobenius error ||A - A_uBLR||_F / ||A||_F (evaluation
+ * harness; not part of the black-box method; Section 7's error metric).
+ * Built-in operators: block by block with entry access.  Black-box operators:
+ * from N products A e_j (unit columns in chunks of at most 512) against the
+ * representation applied to the same columns, which costs N products.
+ * Synchronises the stream.
  */
 blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream, double* rel_err);
 

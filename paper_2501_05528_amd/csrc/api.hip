@@ -1424,6 +1424,38 @@ blr_status blr_error_fro(const blr_ublr* h, const blr_operator* op, void* stream
         hipStream_t s = static_cast<hipStream_t>(stream);
         const DeviceTables& t = d.plan->tables();
         AsyncTemps tmp(s);
+        if (is_callback(o)) {
+            // A black box gives its entries only through products: A e_j for every column j,
+            // in chunks of w unit columns, against the representation applied to the same
+            // columns; both squared norms summed per chunk in a fixed order.
+            const int64_t n = P.n;
+            const int64_t w = std::max<int64_t>(16, std::min<int64_t>(512, ((int64_t(1) << 25) / n) / 16 * 16));
+            double* X = tmp.plain(n * w);
+            double* Y = tmp.plain(n * w);
+            double* R = tmp.get(n * w);
+            double* work = tmp.get(apply_workspace_doubles(P, w));
+            double* part = tmp.get(dot_parts());
+            auto sumsq = [&](const double* v, int64_t len) {
+                launch_dot(v, v, len, part, s);
+                double r = 0.0;
+                HIPC(hipMemcpyAsync(&r, part, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPC(hipStreamSynchronize(s));
+                return r;
+            };
+            double se = 0.0, sa = 0.0;
+            for (int64_t c0 = 0; c0 < n; c0 += w) {
+                const int64_t wc = std::min(w, n - c0);
+                launch_unit_cols(X, n, c0, wc, s);
+                op_apply(o, 0, wc, X, n, Y, n, s);
+                launch_ublr_apply(P, t, d.U, d.V, d.Atil, d.B, 0, wc, X, n, R, n, work, s);
+                sa += sumsq(Y, n * wc);
+                launch_axpy(-1.0, Y, R, n * wc, s);
+                se += sumsq(R, n * wc);
+            }
+            if (!std::isfinite(se) || !std::isfinite(sa)) fail(BLR_ERR_NUMERICAL, "non-finite error sums");
+            *rel_err = sa > 0.0 ? std::sqrt(se / sa) : std::sqrt(se);
+            return;
+        }
         const int64_t np = static_cast<int64_t>(P.b) * P.b;
         double* part = tmp.get(2 * np);
         require_entries(o, "the exact Frobenius error");

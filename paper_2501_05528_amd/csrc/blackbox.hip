@@ -56,6 +56,15 @@ __global__ __launch_bounds__(256) void k_fill0(double* __restrict__ x, int64_t n
     if (idx < n) x[idx] = 0.0;
 }
 
+// X(:, q) = e_{c0 + q} for q < w (n x w, leading dimension n): unit columns for the
+// products that give a black box's entries.
+__global__ __launch_bounds__(256) void k_unit_cols(double* __restrict__ X, int64_t n, int64_t c0, int64_t w) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= n * w) return;
+    const int64_t q = idx / n, row = idx - q * n;
+    X[idx] = row == c0 + q ? 1.0 : 0.0;
+}
+
 // S(row, c) += sum over boxes l in [j0, j1) that are far from box(row), in ascending order,
 // of W(row, (l - j0) w + c): the far-field part of the products of A with a chunk of
 // block-diagonal test columns (w columns per box).
@@ -383,6 +392,11 @@ void launch_to_f32(const double* x, int64_t n, float* y, hipStream_t s) {
 void launch_fill0(double* x, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill0, dim3(blocks_for(n)), dim3(256), 0, s, x, n);
     check_launch_bb("fill");
+}
+
+void launch_unit_cols(double* X, int64_t n, int64_t c0, int64_t w, hipStream_t s) {
+    hipLaunchKernelGGL(k_unit_cols, dim3(blocks_for(n * w)), dim3(256), 0, s, X, n, c0, w);
+    check_launch_bb("unit columns");
 }
 
 void launch_far_gather(const PlanData& P, const DeviceTables& t, const double* W, int w, int j0, int j1,

@@ -124,6 +124,8 @@ void launch_expand_tagged_f32(const PlanData& P, const DeviceTables& t, const do
                               hipStream_t s);
 void launch_to_f32(const double* x, int64_t n, float* y, hipStream_t s);
 void launch_fill0(double* x, int64_t n, hipStream_t s);
+// X (n x w) = columns c0 .. c0 + w - 1 of the identity.
+void launch_unit_cols(double* X, int64_t n, int64_t c0, int64_t w, hipStream_t s);
 void launch_far_gather(const PlanData& P, const DeviceTables& t, const double* W, int w, int j0, int j1,
                        double* S, hipStream_t s);
 // Alg. 3 on a black box: masked test matrices of boxes [i0, i1) (N x (i1 - i0) r) and

@@ -7,8 +7,10 @@ caller's products (Python callback running a dense product on the library's stre
   sketches to 1e-12, every far block U_i Atil_ij V_j* and near block plus B_ij to
   1e-11 max|A|, and the power estimate of ||A - A_uBLR||_2 in the 1.5 band.
 * A failing product ends the call with BLR_ERR_OPERATOR.
-* The exact Frobenius error, which needs entry access, is refused with BLR_ERR_UNSUPPORTED
-  (the mixed-precision modes through a black box are tested in test_gpu_blackbox_mixed.py).
+* The exact Frobenius error takes the entries from N products with unit columns and equals
+  the oracle's error of the same factors; batches, which need entry access, are refused
+  with BLR_ERR_UNSUPPORTED (the mixed-precision modes through a black box are tested in
+  test_gpu_blackbox_mixed.py).
 * The host export returns the same arrays as the device parts.
 """
 import numpy as np
@@ -70,7 +72,7 @@ def run(request):
     torch.cuda.synchronize()
     cols = dict(cnt.cols)
     return dict(P=P, g=g, A=A, Ad=Ad, k=k, p=p, seed=seed, T=T, res=res, plan=plan, op=op, h=h, rep=rep,
-                cols=cols, name=request.param)
+                cols=cols, cnt=cnt, name=request.param)
 
 
 def test_product_counts(run):
@@ -120,11 +122,40 @@ def test_power_error_vs_oracle(run):
     assert (abs(e_gpu - e_or) <= 1e-12 * a_or) or (1 / 1.5 <= e_gpu / e_or <= 1.5)
 
 
-def test_entry_access_modes_refused(run):
-    P, op = run["P"], run["op"]
+def test_error_fro_from_products(run):
+    """blr_error_fro on a black box takes A's entries from N products with unit columns;
+    it must equal the oracle's exact error of the library's own factors (1e-10 relative
+    plus 2e-14) and cost exactly N products of A (none of A*)."""
+    g, k, h = run["g"], run["k"], run["h"]
+    cnt = run["cnt"]
+    before = dict(cnt.cols)
+    e_gpu = h.error_fro(run["op"])
+    assert cnt.cols[0] - before[0] == g.n and cnt.cols[1] == before[1]
+    U, V, At = (h.part(x).cpu().numpy() for x in ("U", "V", "Atil"))
+    Bflat = h.part("B").cpu().numpy()[:, 0]
+    near_ptr, near_idx, _, boff = run["plan"].lists()
+    bp = g.box_ptr
+    B = {}
+    for i in range(g.nboxes):
+        for q in range(near_ptr[i], near_ptr[i + 1]):
+            j = near_idx[q]
+            mi, mj = bp[i + 1] - bp[i], bp[j + 1] - bp[j]
+            B[(i, j)] = Bflat[boff[q]:boff[q] + mi * mj].reshape((mi, mj), order="F")
+    e_same = O.rel_fro_error(O.DenseOperator(run["A"]), U, V, At, B, bp, k)
+    _announce(f"black box {run['name']}: rel fro error from products {e_gpu:.6e}, "
+              f"oracle on the same factors {e_same:.6e}")
+    assert abs(e_gpu - e_same) <= 1e-10 * e_same + 2e-14
+
+
+def test_batch_refused(run):
+    """Batches need entry access: a black-box job is refused with BLR_ERR_UNSUPPORTED."""
+    import torch
+    P, g = run["P"], run["g"]
+    G, H = W.gaussian_test_blocks(run["seed"], g.n, run["k"] + run["p"])
     with pytest.raises(P.BlrError) as ei:
-        run["h"].error_fro(op)
+        P.Batch([dict(plan=run["plan"], op=run["op"], G=P.colmajor(G), H=P.colmajor(H), precision="fp64")])
     assert ei.value.name == "BLR_ERR_UNSUPPORTED"
+    torch.cuda.synchronize()
 
 
 def test_export_matches_parts(run):

@@ -133,6 +133,10 @@ def test_slab_error_and_counts(tagged):
     e_gpu = O.rel_fro_error(tagged["Sd"], out["U"], out["V"], out["Atil"], Bd, g.box_ptr, k)
     _announce(f"slab: error of the library's factors {e_gpu:.3e}, oracle {res['err']:.3e}")
     assert abs(e_gpu - res["err"]) <= 1e-12 or 1 / 1.5 <= e_gpu / res["err"] <= 1.5
+    # the library's own exact error of the same factors, from N products of the black box
+    e_lib = tagged["h"].error_fro(tagged["op"])
+    _announce(f"slab: blr_error_fro from products {e_lib:.6e}, oracle on the same factors {e_gpu:.6e}")
+    assert abs(e_lib - e_gpu) <= 1e-10 * e_gpu + 2e-14
     rep = tagged["rep"]
     ell, r = tagged["plan"].ell, k + 10
     assert rep["applies_At"] == ell * r
