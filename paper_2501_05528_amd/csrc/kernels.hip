@@ -921,7 +921,7 @@ template <class AS>
 void refine_launch(AS A, const PlanData& P, const DeviceTables& t, const double* X0,
                    const double* X1, int nside, double* S0, double* S1, hipStream_t s) {
     const int ntr = (P.r + 15) / 16;
-    constexpr int MAV = 8;  // 128 target rows per workgroup
+    constexpr int MAV = 4;  // 64 target rows per workgroup (32 measured slower)
     const dim3 grid(static_cast<unsigned>((P.n + 16 * MAV - 1) / (16 * MAV)));
 #define BLR_REFINE_CASE(NTRV, NSV)                                                                      \
     hipLaunchKernelGGL((k_refine<AS, NTRV, NSV, MAV>), grid, dim3(256), 0, s, A, t.box_ptr, t.row_box, \
