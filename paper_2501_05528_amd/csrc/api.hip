@@ -470,8 +470,11 @@ blr_status blr_op_kernel_create(int32_t kind, int32_t dim, int64_t n, const doub
         d->device = current_device();
         d->pts = dalloc_sync(3 * n);
         HIPC(hipMemcpy(d->pts, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+        // FP32 copy with 32 zero entries past the end: the low-precision sketch loads a
+        // step's 32 source columns without clamping them to the box
         std::vector<float> soa32(soa.begin(), soa.end());
-        d->pts32 = reinterpret_cast<float*>(dalloc_sync((3 * n + 1) / 2));
+        soa32.resize(soa32.size() + 32, 0.0f);
+        d->pts32 = reinterpret_cast<float*>(dalloc_sync((static_cast<int64_t>(soa32.size()) + 1) / 2));
         HIPC(hipMemcpy(d->pts32, soa32.data(), soa32.size() * sizeof(float), hipMemcpyHostToDevice));
         auto* o = new blr_operator;
         o->d = std::move(d);

@@ -99,7 +99,7 @@ struct OpData {
     const double* A = nullptr;    // dense, borrowed
     int64_t lda = 0;
     double* pts = nullptr;        // kernel: device SoA [3][n] (unused axes zero), owned
-    float* pts32 = nullptr;       // kernel: the same points in FP32, owned
+    float* pts32 = nullptr;       // kernel: the same points in FP32 (+32 zeros at the end), owned
     blr_apply_fn fn = nullptr;    // callback: the caller's products with A and A*
     blr_apply_lp_fn fn_lp = nullptr;  // callback: optional FP32-operand products (mixed modes)
     void* ctx = nullptr;          // callback: the caller's context, borrowed

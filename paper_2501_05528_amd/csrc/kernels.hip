@@ -783,7 +783,10 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
     const int box_first = row_box[row0], box_last = row_box[rlast];
     const bool single = box_first == box_last;
     // generation: thread owns row tid % BM and sources tid / BM + KSTEP u, u < MA
-    const int arow = tid % BM, akk = tid / BM;
+    // with BM a multiple of 64 every thread of a wave takes the same source column in each
+    // entry slot, so the column's points are loaded once per wave (scalar loads)
+    const int arow = tid % BM;
+    const int akk = BM % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / BM) : tid / BM;
     const int64_t gi = min(row0 + arow, n - 1);
     const auto rp = A.row(gi);
     const int64_t mybox_row = static_cast<int64_t>(row_box[gi]) * nbox;

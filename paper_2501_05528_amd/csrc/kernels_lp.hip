@@ -77,6 +77,17 @@ struct KernelSrc32 {
     using Pre = P;
     __device__ Pre pre(const P&, int64_t j) const { return col(j); }
     __device__ float fin(const P& a, const Pre& b) const { return val(a, b); }
+    // column jb + off with jb the same for every thread and 0 <= off < 32: the points
+    // arrays carry 32 readable entries past the end, so no clamp is needed (entries past
+    // the box are discarded by the caller)
+    static constexpr bool kPadded = true;
+    __device__ Pre pre_at(int64_t jb, int off) const {
+        const BLR_GLB float* bx = px + jb;
+        const BLR_GLB float* by = py + jb;
+        const BLR_GLB float* bz = pz + jb;
+        const uint32_t o = static_cast<uint32_t>(off);
+        return P{bx[o], by[o], bz[o], static_cast<int32_t>(jb) + off};
+    }
 };
 
 struct DenseSrc32 {  // A(i, j) = A[i + j*lda], rounded to FP32
@@ -106,6 +117,13 @@ struct DenseTSrc32 {  // (A*)(i, j) = A[j + i*lda], rounded to FP32
     __device__ Pre pre(const P& a, int64_t j) const { return A[j + a.i * lda]; }
     __device__ float fin(const P&, Pre v) const { return static_cast<float>(v); }
 };
+
+// Sources whose point arrays are padded (KernelSrc32::kPadded) load a step's columns
+// without clamping.
+template <class AS, class = void>
+struct PaddedSrc : std::false_type {};
+template <class AS>
+struct PaddedSrc<AS, std::void_t<decltype(AS::kPadded)>> : std::bool_constant<AS::kPadded> {};
 
 template <int PREC>
 struct LpElem;
@@ -240,16 +258,21 @@ __device__ __attribute__((always_inline)) inline void sketch_lp_tile(AS A, const
     auto pre_a = [&](int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t j = jb + akk + 8 * u;
-            apre[u] = A.pre(rp, j < jend ? j : jend - 1);
+            if constexpr (PaddedSrc<AS>::value) {
+                apre[u] = A.pre_at(jb, akk + 8 * u);
+            } else {
+                const int64_t j = jb + akk + 8 * u;
+                apre[u] = A.pre(rp, j < jend ? j : jend - 1);
+            }
         }
     };
     auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
+        const int nvalid = static_cast<int>(min(jend - jb, static_cast<int64_t>(KT)));  // same for all threads
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int kk = akk + 8 * u;
             const float v = A.fin(rp, apre[u]);
-            sA[buf][arow * AST + kk] = jb + kk < jend ? v : 0.0f;
+            sA[buf][arow * AST + kk] = kk < nvalid ? v : 0.0f;
         }
     };
 
