@@ -134,12 +134,23 @@ __device__ inline double log_tab(double x, const BLR_LDS double* tab) {
     return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, L + l1));
 }
 
+// 1 / sqrt(x) for a positive, finite, normal x: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (each squares the relative error; the residual
+// 1 - x y^2 is formed with one fused multiply-add).  About 1 ulp.
+__device__ inline double rsqrt_pos(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 template <int KIND>
 __device__ inline double kval(double r2) {
     if constexpr (KIND == BLR_KERNEL_LOG) {
         return 0.5 * log_pos(r2);
     } else if constexpr (KIND == BLR_KERNEL_INV_R) {
-        return 1.0 / sqrt(r2);
+        return rsqrt_pos(r2);
     } else if constexpr (KIND == BLR_KERNEL_EXP) {
         return exp(-sqrt(r2) / 0.1);
     } else {
