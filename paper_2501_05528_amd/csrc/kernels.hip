@@ -96,17 +96,17 @@ __device__ inline BLR_GLB T* as_glb(T* p) {
     return (BLR_GLB T*)p;
 }
 
-// Table-driven natural logarithm for the kernel-matrix entries.  x = m 2^e with
-// m in [1/sqrt2, sqrt2); the top six mantissa bits of m (and its binade) pick one
-// of 128 centres c with r = 1/c stored beside L = -ln r, so that
-//   ln x = e ln2 + L + ln(1 + f),   f = m r - 1 (one fused multiply-add, |f| <= 2^-7),
-// with ln(1 + f) from its Taylor series to f^8 (truncation below 1e-20).  The table
-// is built per workgroup from log_pos.  Absolute error about 2e-16 for |ln x| < 1.
+// Table-driven natural logarithm for the kernel-matrix entries.  x = m 2^e with m in
+// [1/2, 1); the top seven mantissa bits of m pick one of 128 centres c (spacing 1/256) with
+// r = 1/c stored beside L = -ln r, so that
+//   ln x = e ln2 + L + ln(1 + f),   f = m r - 1 (one fused multiply-add, |f| <= 2^-8),
+// with ln(1 + f) from its Taylor series to f^6 (truncation below 3e-18).  The table is built
+// per workgroup from log_pos.  Absolute error about 2e-16 for |ln x| < 1 (no split of the
+// binade at sqrt 2: the entries need absolute, not relative, accuracy near x = 1).
 __device__ inline void build_log_table(BLR_LDS double* tab) {
     const int t = threadIdx.x;
     if (t < 128) {
-        const double base = t < 64 ? 0.5 : 1.0;
-        const double c = base * (1.0 + ((t & 63) + 0.5) / 64.0);
+        const double c = 0.5 + (t + 0.5) / 256.0;
         const double r = 1.0 / c;
         tab[2 * t] = r;
         tab[2 * t + 1] = -log_pos(r);
@@ -114,17 +114,12 @@ __device__ inline void build_log_table(BLR_LDS double* tab) {
 }
 
 __device__ inline double log_tab(double x, const BLR_LDS double* tab) {
-    const int e0 = __builtin_amdgcn_frexp_exp(x);
-    double m = __builtin_amdgcn_frexp_mant(x);
-    const bool lo = m < 0.7071067811865476;
-    m = lo ? 2.0 * m : m;
-    const int e = lo ? e0 - 1 : e0;
-    const int idx = ((__double2hiint(m) >> 14) & 63) + (m >= 1.0 ? 64 : 0);
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const int idx = (__double2hiint(m) >> 13) & 127;
     const double r = tab[2 * idx], L = tab[2 * idx + 1];
     const double f = fma(m, r, -1.0);
-    double q = -1.0 / 8.0;
-    q = fma(q, f, 1.0 / 7.0);
-    q = fma(q, f, -1.0 / 6.0);
+    double q = -1.0 / 6.0;
     q = fma(q, f, 1.0 / 5.0);
     q = fma(q, f, -1.0 / 4.0);
     q = fma(q, f, 1.0 / 3.0);
