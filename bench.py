@@ -380,7 +380,8 @@ def config_section(S, steps=2, warmup=1, with_error=True):
 
 def planted_section(steps=10):
     """The planted exact-rank workload (64 x 64 grid, 8 x 8 boxes of 64, k = 8, dense A in
-    HBM): compressions/s and the exact error (exact recovery)."""
+    HBM): compressions/s and the exact error (exact recovery), in FP64 and in the BF16 and
+    FP32 mixed modes (one refinement sketch)."""
     import torch
     import paper_2501_05528_amd as P
     wl = W.WORKLOADS["planted_2d_n4096"]
@@ -399,9 +400,23 @@ def planted_section(steps=10):
         h, rep = P.compress(plan, op, G, H, report=True)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
-    return {"value": round(1.0 / el, 3), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 4),
-            "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
-            "rel_err_fro": h.error_fro(op)}
+    out = {"value": round(1.0 / el, 3), "unit": "compressions/s", "ms_per_step": round(1e3 * el, 4),
+           "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+           "rel_err_fro": h.error_fro(op)}
+    gu, gv = W.refinement_gammas(wl.seed, g.nboxes, wl.r, wl.r)
+    kw = dict(gamma_u=torch.as_tensor(gu, device="cuda"), gamma_v=torch.as_tensor(gv, device="cuda"))
+    for prec in ("bf16", "fp32"):
+        h, _ = P.compress(plan, op, G, H, report=True, precision=prec, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h, rep = P.compress(plan, op, G, H, report=True, precision=prec, **kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[prec] = {"value": round(1.0 / el, 3), "ms_per_step": round(1e3 * el, 4),
+                     "applies_per_compression": int(rep["applies_A"] + rep["applies_At"]),
+                     "rel_err_fro": h.error_fro(op)}
+    return out
 
 
 def _blas_threads():
