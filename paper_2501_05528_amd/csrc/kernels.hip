@@ -830,12 +830,15 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
             gv[u] = gptr[u][min(jb + kk, jend - 1)];
         }
     };
-    auto store_b = [&](int buf, int64_t jb, int64_t jend) {
+    // rows past the box and columns past r need no zeroing here: the A tile is zero in
+    // those rows (gen_a) and the padding columns of the accumulators are never stored, and
+    // the values read there are finite rows of X0 / X1
+    auto store_b = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             const int e = tid + 256 * u;
             const int kk = e % KT, cc = e / KT;
-            if (gin[u]) sB[buf][cc * KTP + kk] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+            if (gin[u]) sB[buf][cc * KTP + kk] = gv[u];
         }
     };
     // the next step's kernel columns and far mask are loaded before the current
@@ -877,7 +880,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
         int64_t j0 = box_ptr[l], jend = box_ptr[l + 1];
         fetch_b(j0, jend);
         pre_a(l, j0, jend);
-        store_b(0, j0, jend);
+        store_b(0);
         gen_a(0, j0, jend);
         __syncthreads();
         int buf = 0;
@@ -915,7 +918,7 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
                         for (int nt = 0; nt < NTR; ++nt) acc[sd][ma][nt] = mfma44(a[ma], bb[sd][nt], acc[sd][ma][nt]);
             }
             if (!more) break;
-            store_b(buf ^ 1, jn, jendn);
+            store_b(buf ^ 1);
             gen_a(buf ^ 1, jn, jendn);
             __syncthreads();
             buf ^= 1;
