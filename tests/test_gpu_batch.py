@@ -145,3 +145,35 @@ def test_footprint(batch_setup):
         out_bytes = 8 * (2 * plan.n * plan.k + (plan.b * plan.k) ** 2 + plan.info["b_values"])
         for prec in ("fp64", "bf16", "fp32"):
             assert P.footprint(plan, prec) > out_bytes
+
+
+def test_fp64_class_with_different_tag_counts():
+    """Two FP64 1/r jobs with 4 column tiles of r in one persistent class: a 2D one (ell = 13,
+    two groups of 6 and 7 tag columns, 2 per wave would do) and a 3D one (ell = 31, three groups
+    of 10 or 11, 3 per wave needed).  The class takes the larger tag-columns-per-wave, and both
+    jobs' results equal their single-job compressions bit for bit."""
+    import torch
+    import paper_2501_05528_amd as P
+    specs = []
+    for dim, B, q, seed in ((2, 6, 8, 20250201), (3, 4, 4, 20250202)):
+        g = W.grid_geometry(dim, B, q)
+        k, p = 48, 10                                   # r = 58: four 16-column tiles
+        near = O.near_lists(g.lattice)
+        T = W.tag_matrix(seed, g.nboxes, O.num_tag_columns(near, 3))
+        G, H = W.gaussian_test_blocks(seed, g.n, k + p)
+        plan = P.Plan(g.box_ptr, g.lattice, k, T, p=p, extra_tag_cols=3)
+        specs.append(dict(plan=plan, op=P.Operator.kernel("inv_r", g.pts), G=P.colmajor(G), H=P.colmajor(H),
+                          n=g.n, ell=plan.ell))
+        _announce(f"fp64 class job: dim={dim} N={g.n} b={g.nboxes} ell={plan.ell} r={k + p}")
+    singles = []
+    for sp in specs:
+        h, _ = P.compress(sp["plan"], sp["op"], sp["G"], sp["H"])
+        singles.append({x: h.part(x) for x in ("U", "V", "Atil", "B")})
+    b = P.Batch([dict(plan=s["plan"], op=s["op"], G=s["G"], H=s["H"], precision="fp64") for s in specs],
+                graph=False, autotune=False)
+    rep = b.run()
+    torch.cuda.synchronize()
+    assert rep["nclasses"] == 1 and rep["class_precision"] == [0] and rep["class_ntr"] == [4]
+    assert rep["class_kind"] == [KIND_CODE["inv_r"]] and rep["class_jobs"] == [2]
+    assert rep["class_spw"] == [3]
+    _check_equal(b, singles)
