@@ -284,7 +284,9 @@ def rank_section(S, tol=1e-8, k_probe=48, p=10):
     log(f"rank for tol {tol:.0e}: k = {k} ({1e3 * t_rank:.1f} ms), compression {rep['ms_total']:.1f} ms, "
         f"rel err {err:.2e}")
     return {"tol": tol, "k_probe": k_probe, "k": k, "ms_rank": round(1e3 * t_rank, 3),
-            "ms_compress": round(rep["ms_total"], 3), "rel_err_fro": err}
+            "ms_compress": round(rep["ms_total"], 3), "rel_err_fro": err,
+            "note": "uniform k from a per-direction singular-value threshold (no error bound); the "
+                    "tolerance-calibrated path is the per-box truncation (`truncation`)"}
 
 
 def truncation_section(S, tol=1e-8, k_big=48, p=10):
