@@ -57,6 +57,9 @@ def _case(name):
     if name == "line1d_k13":            # d = 1 (3 neighbours, ell = 7), odd rank
         g = W.grid_geometry(1, 24, 90, jitter=0.2, seed=13)
         return dict(name=name, g=g, k=13, p=10, kind="exp", seed=20250107)
+    if name == "square_samples":        # r = k + p equals the box size: square m x r samples
+        g = W.grid_geometry(2, 7, 6, jitter=0.2, seed=17)
+        return dict(name=name, g=g, k=26, p=10, kind="log", seed=20250108)
     if name == "cos_uneven":
         g = W.irregular_grid_geometry([[9, 12, 10, 14, 11, 9], [10, 13, 9, 12, 11]], jitter=0.2, seed=9)
         return dict(name=name, g=g, k=20, p=10, kind="cos", seed=20250105)
@@ -64,7 +67,7 @@ def _case(name):
 
 
 CASES = ["planted", "laplace_n9216", "laplace_ragged_jitter", "invr3d_n8000", "exp_n2500", "cos_uneven",
-         "log_boxes306", "line1d_k13"]
+         "log_boxes306", "line1d_k13", "square_samples"]
 
 
 def _oracle(c):
