@@ -579,7 +579,7 @@ def batch_section(njobs=96, seed=20250104, n_lo=4096, n_hi=65536):
             "batched_fp64_sketch_ms": round(rep64["ms_sketch"], 3),
             "batched_fp64_sketch_tflops": round(rep64["sketch_flops"] / (rep64["ms_sketch"] * 1e-3) / 1e12, 2),
             "batched_fp64_classes": {"ntr": rep64["class_ntr"], "kind": rep64["class_kind"],
-                                     "jobs": rep64["class_jobs"]},
+                                     "tail": rep64["class_tail"], "jobs": rep64["class_jobs"]},
             "batched_fp64_err_rel_diff_first4": e64b,
             "batched_fp32_jobs_per_s": round(njobs / tb, 3),
             "speedup": round(t64 / tb, 3),

@@ -612,11 +612,15 @@ typedef struct blr_batch_report {
     int64_t applies;          /* sum over jobs of the products in the paper's convention */
     int32_t graph_replayed;   /* 1 if this run replayed the captured graph */
     int32_t nclasses;         /* persistent sketch launches: one per (precision, 16-column tiles)
-                                 and, for FP64, per kernel kind */
+                                 and, for FP64, per kernel kind and form of the last column tile */
     int32_t class_precision[BLR_BATCH_MAX_CLASSES], class_ntr[BLR_BATCH_MAX_CLASSES];
     int32_t class_spw[BLR_BATCH_MAX_CLASSES];   /* tag columns per wave of the launch */
     int32_t class_jobs[BLR_BATCH_MAX_CLASSES];
     int32_t class_kind[BLR_BATCH_MAX_CLASSES];  /* blr_kernel_kind of an FP64 class, -1 otherwise */
+    int32_t class_tail[BLR_BATCH_MAX_CLASSES];  /* FP64 class: 3 when the last 16-column tile (at
+                                                   most 12 of the r columns) runs in the narrow form,
+                                                   the choice blr_tag_compress makes for the same
+                                                   kernel kind and r; else 0 */
 } blr_batch_report;
 
 /*

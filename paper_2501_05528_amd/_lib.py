@@ -62,7 +62,8 @@ class BatchReport(ctypes.Structure):
                 ("refine_flops", c_double), ("applies", c_int64), ("graph_replayed", c_int32),
                 ("nclasses", c_int32), ("class_precision", c_int32 * BATCH_MAX_CLASSES),
                 ("class_ntr", c_int32 * BATCH_MAX_CLASSES), ("class_spw", c_int32 * BATCH_MAX_CLASSES),
-                ("class_jobs", c_int32 * BATCH_MAX_CLASSES), ("class_kind", c_int32 * BATCH_MAX_CLASSES)]
+                ("class_jobs", c_int32 * BATCH_MAX_CLASSES), ("class_kind", c_int32 * BATCH_MAX_CLASSES),
+                ("class_tail", c_int32 * BATCH_MAX_CLASSES)]
 
 
 class ServerJobStats(ctypes.Structure):

@@ -392,7 +392,7 @@ class Batch:
         check(lib().blr_batch_run(self._h, _stream(stream), byref(rep)))
         out = {f: getattr(rep, f) for f, _ in _lib.BatchReport._fields_}
         nc = rep.nclasses
-        for f in ("class_precision", "class_ntr", "class_spw", "class_jobs", "class_kind"):
+        for f in ("class_precision", "class_ntr", "class_spw", "class_jobs", "class_kind", "class_tail"):
             out[f] = list(getattr(rep, f))[:nc]
         return out
 

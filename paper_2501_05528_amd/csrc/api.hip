@@ -1599,6 +1599,7 @@ struct BatchJob {
 struct SketchClass {
     int precision = 0, ntr = 0;
     int kind = -1;                 // FP64 classes: the kernel kind of every member
+    int tg = 0;                    // FP64 classes: fp64_sketch_tail_groups(kind, r) of every member
     std::vector<int> members;
     LpJob* d_jobs = nullptr;
     Fp64Job* d_jobs64 = nullptr;
@@ -1669,7 +1670,7 @@ void batch_enqueue(blr_batch& B, bool time_sketch) {
     if (time_sketch) HIPC(hipEventRecord(B.e0, s));
     for (auto& c : B.classes) {
         if (c.precision == BLR_PREC_FP64)
-            launch_sketch_multi(c.kind, c.ntr, c.spw[0], c.d_jobs64, c.d_items[0], c.nitems[0], B.grid, s);
+            launch_sketch_multi(c.kind, c.ntr, c.spw[0], c.tg, c.d_jobs64, c.d_items[0], c.nitems[0], B.grid, s);
         else
             launch_sketch_lp_multi(c.precision, c.ntr, c.spw[c.chosen], c.d_jobs, c.d_items[c.chosen],
                                    c.nitems[c.chosen], B.grid, s);
@@ -1811,15 +1812,18 @@ blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t fl
             j.Zh = B->alloc<double>(P.n * j.r_lo);
             j.nfw = B->alloc<double>(nearfield_workspace_doubles(P));
         }
-        // persistent sketch classes: (precision, column tiles), FP64 also by kernel kind
+        // persistent sketch classes: (precision, column tiles), FP64 also by kernel kind and
+        // the form of the last column tile
         for (int q = 0; q < njobs; ++q) {
             BatchJob& j = B->jobs[q];
             if (!j.persistent) continue;
             const int ntr = (j.r_lo + 15) / 16;
-            const int kind = j.precision == BLR_PREC_FP64 ? j.op->kind : -1;
+            const bool f64 = j.precision == BLR_PREC_FP64;
+            const int kind = f64 ? j.op->kind : -1;
+            const int tg = f64 ? fp64_sketch_tail_groups(kind, j.r_lo) : 0;
             SketchClass* c = nullptr;
             for (auto& x : B->classes)
-                if (x.precision == j.precision && x.ntr == ntr && x.kind == kind) c = &x;
+                if (x.precision == j.precision && x.ntr == ntr && x.kind == kind && x.tg == tg) c = &x;
             if (!c) {
                 if (B->classes.size() >= BLR_BATCH_MAX_CLASSES) fail(BLR_ERR_UNSUPPORTED, "too many sketch classes");
                 B->classes.emplace_back();
@@ -1827,6 +1831,7 @@ blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t fl
                 c->precision = j.precision;
                 c->ntr = ntr;
                 c->kind = kind;
+                c->tg = tg;
             }
             c->members.push_back(q);
         }
@@ -2019,6 +2024,7 @@ blr_status blr_batch_run(blr_batch* b, void* stream, blr_batch_report* rep) {
             for (size_t q = 0; q < b->classes.size(); ++q) {
                 rep->class_precision[q] = b->classes[q].precision;
                 rep->class_kind[q] = b->classes[q].kind;
+                rep->class_tail[q] = b->classes[q].tg;
                 rep->class_ntr[q] = b->classes[q].ntr;
                 rep->class_spw[q] = b->classes[q].spw[b->classes[q].chosen];
                 rep->class_jobs[q] = static_cast<int32_t>(b->classes[q].members.size());

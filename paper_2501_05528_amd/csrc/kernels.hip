@@ -169,6 +169,7 @@ __device__ inline double kval(double r2) {
 
 template <int KIND>
 struct KernelSrc {
+    static constexpr int kKind = KIND;
     const double* px;
     const double* py;
     const double* pz;
@@ -213,6 +214,7 @@ struct KernelSrc {
 };
 
 struct DenseSrc {  // A(i, j) = A[i + j*lda]
+    static constexpr int kKind = -1;
     const double* A;
     int64_t lda;
     __device__ void prepare(BLR_LDS double*) {}
@@ -231,6 +233,7 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
 };
 
 struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
+    static constexpr int kKind = -1;
     const double* A;
     int64_t lda;
     __device__ void prepare(BLR_LDS double*) {}
@@ -444,6 +447,12 @@ void gemm_launch(AS A, BS B, OUT O, int64_t M, int64_t K, int ncols, hipStream_t
 // blocks, i.e. one 4 x 16 x 4 product per instruction:
 //   A lane l: A[l % 4][l / 16];  B lane l: B[l / 16][l % 16];
 //   D lane l: D[l / 16][l % 16].
+// When the last 16-column tile of a two-sided sketch holds at most 12 of the
+// r columns (TG = 3, chosen by fp64_sketch_tail_groups where it measured
+// faster), it runs in a narrow form instead: the four blocks take
+// (4-row quad, 4-source half of an 8-source slice) pairs against 4 columns, so
+// its 12 columns cost 3 instructions per 8 sources where the 4 x 16 x 4 form
+// spends 4 (r = 42: 11 instead of 12 MFMAs per 4 sources and tag column).
 // Tiles are double-buffered in LDS with one barrier per step; the next
 // step's [G|H] rows are fetched into registers before the current step's
 // MFMAs and stored afterwards.
@@ -455,13 +464,17 @@ __device__ inline double mfma44(double a, double b, double c) {
 // column group grp of ngroups.  The split of the tag columns over groups and waves does
 // not change any column's arithmetic.  sAp / sBp: the double-buffered LDS tiles (2 x KT*BM and
 // 2 x (KT+1)*BW doubles).
-template <class AS, int NTR, int NSIDE, int SVW, int KT, bool EVEN>
+template <class AS, int NTR, int NSIDE, int SVW, int KT, bool EVEN, int TG>
 __device__ __attribute__((always_inline)) inline void sketch_tile(
     const AS& A, const double* __restrict__ T, const int64_t* __restrict__ box_ptr, int nbox,
     const double* __restrict__ G0, const double* __restrict__ G1, int64_t n, int r, int ell,
     double* __restrict__ Y0, double* __restrict__ Y1, int64_t rt_blk, int grp, int ngroups,
     BLR_LDS double* sAp, BLR_LDS double* sBp, int tid) {
     constexpr int MA = 2, BM = 4 * MA, CW = NTR * 16;            // rows, cols/side (KT sources/step)
+    // TG > 0: the last 16-column tile holds at most 4 TG columns and runs in the narrow form
+    constexpr int NTRF = TG > 0 ? NTR - 1 : NTR;                 // tiles in the 4 x 16 x 4 form
+    constexpr int TGA = TG > 0 ? TG : 1;
+    static_assert(TG >= 0 && TG <= 3 && KT % 8 == 0, "tile shape");
     constexpr int BW = NSIDE * CW;                               // B tile width
     constexpr int BPT = (KT * BW + 255) / 256;
     constexpr int AGEN = BM * KT;                                // A tile entries per step
@@ -524,15 +537,25 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
         if (agen) sA[buf][akk * BM + arow] = A.fin(rp, apre);
     };
 
-    double acc[SVW][NSIDE][MA][NTR];
+    double acc[SVW][NSIDE][MA][NTRF > 0 ? NTRF : 1];
+    double acct[SVW][NSIDE][TGA];
 #pragma unroll
     for (int v = 0; v < SVW; ++v)
 #pragma unroll
-        for (int sd = 0; sd < NSIDE; ++sd)
+        for (int sd = 0; sd < NSIDE; ++sd) {
 #pragma unroll
             for (int ma = 0; ma < MA; ++ma)
 #pragma unroll
-                for (int nt = 0; nt < NTR; ++nt) acc[v][sd][ma][nt] = 0.0;
+                for (int nt = 0; nt < NTRF; ++nt) acc[v][sd][ma][nt] = 0.0;
+#pragma unroll
+            for (int tg = 0; tg < TGA; ++tg) acct[v][sd][tg] = 0.0;
+        }
+    // narrow form of the last tile: v_mfma_f64_4x4x4f64 with its four blocks indexed by
+    // (4-row quad q, source half h) = (b & 1, b >> 1), b = (lane >> 2) & 3: block b takes rows
+    // 4q..4q+3, sources 8j + 4h..8j + 4h + 3 of an 8-source slice j and 4 columns, so one
+    // instruction covers 8 rows x 4 columns x 8 sources; the two source halves are added
+    // at the end
+    const int tq = (lane >> 2) & 1, th = (lane >> 3) & 1;
 
     int l = 0;
     int64_t j0 = box_ptr[0], jend = box_ptr[1];
@@ -566,28 +589,54 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
         }
 #pragma unroll
         for (int ks = 0; ks < KT / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            double a[MA];
+            if constexpr (NTRF > 0) {
+                const int kr = ks * 4 + (lane >> 4);
+                double a[MA];
 #pragma unroll
-            for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + ma * 4 + (lane & 3)];
-            double bb[NSIDE][NTR];
+                for (int ma = 0; ma < MA; ++ma) a[ma] = sA[buf][kr * BM + ma * 4 + (lane & 3)];
+                double bb[NSIDE][NTRF > 0 ? NTRF : 1];
 #pragma unroll
-            for (int sd = 0; sd < NSIDE; ++sd)
+                for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
-                for (int nt = 0; nt < NTR; ++nt) bb[sd][nt] = sB[buf][(sd * CW + nt * 16 + (lane & 15)) * KTP + kr];
+                    for (int nt = 0; nt < NTRF; ++nt)
+                        bb[sd][nt] = sB[buf][(sd * CW + nt * 16 + (lane & 15)) * KTP + kr];
 #pragma unroll
-            for (int v = 0; v < SVW; ++v) {
-                if (v < nsv) {
-                    double as[MA];
+                for (int v = 0; v < SVW; ++v) {
+                    if (v < nsv) {
+                        double as[MA];
 #pragma unroll
-                    for (int ma = 0; ma < MA; ++ma) as[ma] = a[ma] * tw[v];
+                        for (int ma = 0; ma < MA; ++ma) as[ma] = a[ma] * tw[v];
+#pragma unroll
+                        for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                            for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+                                for (int nt = 0; nt < NTRF; ++nt)
+                                    acc[v][sd][ma][nt] = mfma44(as[ma], bb[sd][nt], acc[v][sd][ma][nt]);
+                    }
+                }
+            }
+            if constexpr (TG > 0) {
+                if (ks & 1) {
+                    const int kt = (ks >> 1) * 8 + th * 4 + (lane >> 4);
+                    const double at = sA[buf][kt * BM + tq * 4 + (lane & 3)];
+                    double bt[NSIDE][TGA];
 #pragma unroll
                     for (int sd = 0; sd < NSIDE; ++sd)
 #pragma unroll
-                        for (int ma = 0; ma < MA; ++ma)
+                        for (int tg = 0; tg < TG; ++tg)
+                            bt[sd][tg] = sB[buf][(sd * CW + NTRF * 16 + tg * 4 + (lane & 3)) * KTP + kt];
 #pragma unroll
-                            for (int nt = 0; nt < NTR; ++nt)
-                                acc[v][sd][ma][nt] = mfma44(as[ma], bb[sd][nt], acc[v][sd][ma][nt]);
+                    for (int v = 0; v < SVW; ++v) {
+                        if (v < nsv) {
+                            const double ats = at * tw[v];
+#pragma unroll
+                            for (int sd = 0; sd < NSIDE; ++sd)
+#pragma unroll
+                                for (int tg = 0; tg < TG; ++tg)
+                                    acct[v][sd][tg] = mfma44(ats, bt[sd][tg], acct[v][sd][tg]);
+                        }
+                    }
                 }
             }
         }
@@ -614,16 +663,26 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
             for (int ma = 0; ma < MA; ++ma) {
                 const int64_t row = row0 + ma * 4 + (lane >> 4);
 #pragma unroll
-                for (int nt = 0; nt < NTR; ++nt) {
+                for (int nt = 0; nt < NTRF; ++nt) {
                     const int c = nt * 16 + (lane & 15);
                     if (row < n && c < r) Yo[row + static_cast<int64_t>(sv * r + c) * n] = acc[v][sd][ma][nt];
+                }
+            }
+            if constexpr (TG > 0) {
+                const int64_t row = row0 + tq * 4 + (lane >> 4);
+#pragma unroll
+                for (int tg = 0; tg < TG; ++tg) {
+                    // lanes l and l ^ 8 hold the two source halves of one output
+                    const double sum = acct[v][sd][tg] + __shfl_xor(acct[v][sd][tg], 8);
+                    const int c = NTRF * 16 + tg * 4 + (lane & 3);
+                    if (th == 0 && row < n && c < r) Yo[row + static_cast<int64_t>(sv * r + c) * n] = sum;
                 }
             }
         }
     }
 }
 
-template <class AS, int NTR, int NSIDE, int SVW, int KT>
+template <class AS, int NTR, int NSIDE, int SVW, int KT, int TG>
 __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restrict__ T,
                                                     const int64_t* __restrict__ box_ptr, int nbox,
                                                     const double* __restrict__ G0,
@@ -636,7 +695,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
     __shared__ double sB[2 * (KT + 1) * BW];
     A.prepare((BLR_LDS double*)s_ltab);
     __syncthreads();
-    sketch_tile<AS, NTR, NSIDE, SVW, KT, false>(A, T, box_ptr, nbox, G0, G1, n, r, ell, Y0, Y1, blockIdx.x,
+    sketch_tile<AS, NTR, NSIDE, SVW, KT, false, TG>(A, T, box_ptr, nbox, G0, G1, n, r, ell, Y0, Y1, blockIdx.x,
                                                 blockIdx.y, gridDim.y, (BLR_LDS double*)sA, (BLR_LDS double*)sB,
                                                 static_cast<int>(threadIdx.x));
 }
@@ -649,7 +708,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
 // allows it (for ell = 13 and 4 column tiles: 2 groups of 6 and 7 instead of 12 and 1, and
 // no spills).  Each tag column's sums run in the same order as in k_sketch, so a job's Y
 // and Z equal its single-job sketch bit for bit.
-template <int KIND, int NTR, int SVW>
+template <int KIND, int NTR, int SVW, int TG>
 __global__ __launch_bounds__(256, 2) void k_sketch_multi(const Fp64Job* __restrict__ jobs,
                                                          const int4* __restrict__ items, int nitems) {
     constexpr int KT = 32, BM = 8, BW = 2 * NTR * 16;
@@ -668,7 +727,7 @@ __global__ __launch_bounds__(256, 2) void k_sketch_multi(const Fp64Job* __restri
         A.pz = (const double*)as_glb(J.pz);
         A.diag = J.diag;
         __syncthreads();  // the table is built; the previous item's last reads of LDS are done
-        sketch_tile<KernelSrc<KIND>, NTR, 2, SVW, KT, true>(
+        sketch_tile<KernelSrc<KIND>, NTR, 2, SVW, KT, true, TG>(
             A, (const double*)as_glb(J.T), (const int64_t*)as_glb(J.box_ptr), J.nbox,
             (const double*)as_glb(J.G0), (const double*)as_glb(J.G1), J.n, J.r, J.ell,
             (double*)as_glb(J.Y0), (double*)as_glb(J.Y1), w.y, w.z, J.ngroups, lA, lB,
@@ -685,16 +744,23 @@ void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double*
     const int svw = std::max(1, std::min(8, 48 / acc_per_sv));
     const int groups = (P.ell + 4 * svw - 1) / (4 * svw);
     dim3 grid((P.n + 7) / 8, groups);
-#define BLR_SKETCH_CASE(NTRV, NSV, SVWV)                                                             \
-    hipLaunchKernelGGL((k_sketch<AS, NTRV, NSV, SVWV, 32>), grid, dim3(256), 0, s, A, t.T, t.box_ptr, \
+#define BLR_SKETCH_CASE_TG(NTRV, NSV, SVWV, TGV)                                                          \
+    hipLaunchKernelGGL((k_sketch<AS, NTRV, NSV, SVWV, 32, TGV>), grid, dim3(256), 0, s, A, t.T, t.box_ptr, \
                        P.b, G0, G1, P.n, P.r, P.ell, Y0, Y1)
+#define BLR_SKETCH_CASE(NTRV, NSV, SVWV) BLR_SKETCH_CASE_TG(NTRV, NSV, SVWV, 0)
+// both sides: the last column tile in the narrow form when it holds at most 12 columns
+#define BLR_SKETCH_CASE2(NTRV, SVWV)                                           \
+    do {                                                                       \
+        if (fp64_sketch_tail_groups(AS::kKind, P.r) == 3) BLR_SKETCH_CASE_TG(NTRV, 2, SVWV, 3); \
+        else BLR_SKETCH_CASE(NTRV, 2, SVWV);                                   \
+    } while (0)
     if (nside == 2) {
         switch (ntr) {
-            case 1: BLR_SKETCH_CASE(1, 2, 8); break;  // 48 / 4 = 12 -> 8
-            case 2: BLR_SKETCH_CASE(2, 2, 6); break;
-            case 3: BLR_SKETCH_CASE(3, 2, 4); break;
-            case 4: BLR_SKETCH_CASE(4, 2, 3); break;
-            case 5: BLR_SKETCH_CASE(5, 2, 2); break;
+            case 1: BLR_SKETCH_CASE2(1, 8); break;  // 48 / 4 = 12 -> 8
+            case 2: BLR_SKETCH_CASE2(2, 6); break;
+            case 3: BLR_SKETCH_CASE2(3, 4); break;
+            case 4: BLR_SKETCH_CASE2(4, 3); break;
+            case 5: BLR_SKETCH_CASE2(5, 2); break;
             default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the sketch kernel");
         }
     } else {
@@ -707,7 +773,9 @@ void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double*
             default: fail(BLR_ERR_UNSUPPORTED, "k + p > 80 is not supported by the sketch kernel");
         }
     }
+#undef BLR_SKETCH_CASE2
 #undef BLR_SKETCH_CASE
+#undef BLR_SKETCH_CASE_TG
     check_launch("tagged sketch");
 }
 
@@ -715,14 +783,27 @@ void sketch_launch(AS A, const PlanData& P, const DeviceTables& t, const double*
 
 int fp64_sketch_svw(int ntr) { return std::max(1, std::min(8, 12 / std::max(1, ntr))); }
 
-void launch_sketch_multi(int kind, int ntr, int svw, const Fp64Job* jobs, const int4* items, int nitems,
-                         int grid, hipStream_t s) {
+int fp64_sketch_tail_groups(int kind, int r) {
+    const int ntr = (r + 15) / 16;
+    if (r <= 0 || r - 16 * (ntr - 1) > 12) return 0;
+    // measured on MI355X: faster with 2 or 3 column tiles for every entry source; with 4 only
+    // for 1/r (exp and cos spill registers there and run slower, log gains nothing)
+    return ntr == 2 || ntr == 3 || (ntr == 4 && kind == BLR_KERNEL_INV_R) ? 3 : 0;
+}
+
+void launch_sketch_multi(int kind, int ntr, int svw, int tg, const Fp64Job* jobs, const int4* items,
+                         int nitems, int grid, hipStream_t s) {
     if (nitems <= 0) return;
+    if (tg != 0 && tg != 3) fail(BLR_ERR_INVALID_ARG, "tail form of the persistent FP64 sketch must be 0 or 3");
     const dim3 g(static_cast<unsigned>(std::max(1, std::min(grid, nitems))));
     auto run = [&](auto kc) {
         constexpr int K = decltype(kc)::value;
         // SVW: fp64_sketch_svw(ntr) or one less
-#define BLR_MULTI(NTRV, SVWV) hipLaunchKernelGGL((k_sketch_multi<K, NTRV, SVWV>), g, dim3(256), 0, s, jobs, items, nitems)
+#define BLR_MULTI(NTRV, SVWV)                                                                                 \
+    do {                                                                                                      \
+        if (tg == 3) hipLaunchKernelGGL((k_sketch_multi<K, NTRV, SVWV, 3>), g, dim3(256), 0, s, jobs, items, nitems); \
+        else hipLaunchKernelGGL((k_sketch_multi<K, NTRV, SVWV, 0>), g, dim3(256), 0, s, jobs, items, nitems);        \
+    } while (0)
         if (ntr == 1 && svw == 8) BLR_MULTI(1, 8);
         else if (ntr == 1 && svw == 7) BLR_MULTI(1, 7);
         else if (ntr == 2 && svw == 6) BLR_MULTI(2, 6);

@@ -78,11 +78,16 @@ struct Fp64Job {
 // Most tag columns per wave of the FP64 sketch for r = 16 ntr columns per side, both
 // sides (the single-job choice); a workgroup covers 4 of them per group.
 int fp64_sketch_svw(int ntr);
+// Form of the last 16-column tile of the two-sided FP64 sketch for r columns per side and
+// an entry source of the given kernel kind (-1: a dense matrix): 3 for the narrow form
+// (three 4-column groups; the tile holds at most 12 columns), else 0.
+int fp64_sketch_tail_groups(int kind, int r);
 // Persistent FP64 sketch over items (job, 8-row block, tag column group) of jobs of
 // one kernel kind; svw is fp64_sketch_svw(ntr) or one less, and every job's groups
-// hold at most 4 svw tag columns.  Grid workgroups stride over the items.
-void launch_sketch_multi(int kind, int ntr, int svw, const Fp64Job* jobs, const int4* items, int nitems,
-                         int grid, hipStream_t s);
+// hold at most 4 svw tag columns; tg is fp64_sketch_tail_groups(kind, r) of every job.  Grid
+// workgroups stride over the items.
+void launch_sketch_multi(int kind, int ntr, int svw, int tg, const Fp64Job* jobs, const int4* items,
+                         int nitems, int grid, hipStream_t s);
 // Tag columns per wave (SPW) offered to the autotuner for a (precision, column
 // tiles) class; a workgroup covers 2 SPW tag columns.  Returns the count (<= 2).
 int lp_multi_spw_candidates(int precision, int ntr, int* spw);

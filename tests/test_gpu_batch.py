@@ -108,13 +108,21 @@ def test_batch_equals_single_jobs_eager_and_graph(batch_setup):
     for prec, ntr, spw in zip(rep2["class_precision"], rep2["class_ntr"], rep2["class_spw"]):
         assert spw in SPW_CANDIDATES[prec][ntr]
     # every kernel-matrix job sketches in a persistent launch: FP64 jobs in classes of one
-    # kernel kind and column-tile count
+    # kernel kind, column-tile count and last-tile form (narrow when it holds <= 12 columns)
     fp64 = [sp for sp in specs if sp["precision"] == "fp64" and "A" not in sp]
     assert sum(nj for prec, nj in zip(rep2["class_precision"], rep2["class_jobs"]) if prec == 0) == len(fp64)
-    want = sorted({(KIND_CODE[sp["wl"].kind], (sp["wl"].k + sp["wl"].p + 15) // 16) for sp in fp64})
-    got = sorted((kd, ntr) for prec, kd, ntr in zip(rep2["class_precision"], rep2["class_kind"],
-                                                    rep2["class_ntr"]) if prec == 0)
+
+    def tail_form(kind, r):
+        ntr = (r + 15) // 16
+        narrow = ntr in (2, 3) or (ntr == 4 and kind == "inv_r")
+        return 3 if narrow and r - 16 * (ntr - 1) <= 12 else 0
+
+    want = sorted({(KIND_CODE[sp["wl"].kind], (sp["wl"].k + sp["wl"].p + 15) // 16,
+                    tail_form(sp["wl"].kind, sp["wl"].k + sp["wl"].p)) for sp in fp64})
+    got = sorted((kd, ntr, tl) for prec, kd, ntr, tl in zip(rep2["class_precision"], rep2["class_kind"],
+                                                            rep2["class_ntr"], rep2["class_tail"]) if prec == 0)
     assert got == want, (got, want)
+    assert all(tl == 0 for prec, tl in zip(rep2["class_precision"], rep2["class_tail"]) if prec != 0)
     assert rep2["sketch_flops"] > 0 and rep2["applies"] > 0
 
 
@@ -175,5 +183,5 @@ def test_fp64_class_with_different_tag_counts():
     torch.cuda.synchronize()
     assert rep["nclasses"] == 1 and rep["class_precision"] == [0] and rep["class_ntr"] == [4]
     assert rep["class_kind"] == [KIND_CODE["inv_r"]] and rep["class_jobs"] == [2]
-    assert rep["class_spw"] == [3]
+    assert rep["class_spw"] == [3] and rep["class_tail"] == [3]     # r = 58: 10 columns in the last tile
     _check_equal(b, singles)
