@@ -519,22 +519,27 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
             gv[u] = gptr[u][min(jb + kk, jend - 1)];
         }
     };
-    auto store_b = [&](int buf, int64_t jb, int64_t jend) {
+    // the B tile is stored as read: rows past the box hold finite rows of the clamped read and
+    // are cancelled by zero A entries (gen_a), and columns past r (read from column 0) only
+    // reach output columns that are never stored
+    auto store_b = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < BPT; ++u) {
             const int e = tid + 256 * u;
             const int kk = e % KT, cc = e / KT;
-            if (gin[u]) sB[buf][cc * KTP + kk] = (gcol[u] && jb + kk < jend) ? gv[u] : 0.0;
+            if (gin[u]) sB[buf][cc * KTP + kk] = gv[u];
         }
     };
     // the next step's kernel column is loaded before the current step's MFMAs
-    // (pre_a) and turned into an entry after them (gen_a)
+    // (pre_a) and turned into an entry after them (gen_a); sources past the box give 0
     typename AS::Pre apre;
+    bool ain = true;
     auto pre_a = [&](int64_t jb, int64_t jend) {
+        ain = jb + akk < jend;
         if (agen) apre = A.pre(rp, min(jb + akk, jend - 1));
     };
     auto gen_a = [&](int buf) {
-        if (agen) sA[buf][akk * BM + arow] = A.fin(rp, apre);
+        if (agen) sA[buf][akk * BM + arow] = ain ? A.fin(rp, apre) : 0.0;
     };
 
     double acc[SVW][NSIDE][MA][NTRF > 0 ? NTRF : 1];
@@ -567,7 +572,7 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
     fetch_b(j0, jend);
     pre_a(j0, jend);
     load_tw(tw, 0);
-    store_b(0, j0, jend);
+    store_b(0);
     gen_a(0);
     __syncthreads();
     int buf = 0;
@@ -641,7 +646,7 @@ __device__ __attribute__((always_inline)) inline void sketch_tile(
             }
         }
         if (!more) break;
-        store_b(buf ^ 1, jn, jendn);
+        store_b(buf ^ 1);
         gen_a(buf ^ 1);
         __syncthreads();
         buf ^= 1;
