@@ -629,16 +629,18 @@ typedef struct blr_batch_report {
  * launches whose workgroups stride over (job, row block, tag column group) items,
  * heaviest job first: mixed-precision jobs one launch per (precision, 16-column
  * tiles of r_lo) class (32-row blocks, every kernel kind in one launch), FP64 jobs
- * one per (16-column tiles of r, kernel kind) class (8-row blocks).  At most
- * BLR_BATCH_MAX_CLASSES classes (else BLR_ERR_UNSUPPORTED).  Every other stage runs
- * per job; jobs on dense operators use the single-job sketch kernels.  Black-box
+ * one per (16-column tiles of r, kernel kind, last-tile form) class (8-row blocks).
+ * At most BLR_BATCH_MAX_CLASSES classes (else BLR_ERR_UNSUPPORTED).  Every other stage
+ * runs per job, the jobs spread over up to 4 streams of the batch (default priority)
+ * forked after the sketches; jobs on dense operators use the single-job sketch
+ * kernels.  Black-box
  * (callback) operators are not supported (BLR_ERR_UNSUPPORTED).  flags:
  * BLR_BATCH_GRAPH, BLR_BATCH_AUTOTUNE (low-precision classes only).
  */
 blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t flags, blr_batch** out);
 
 /*
- * Runs every compression of the batch on the batch's own stream, ordered after
+ * Runs every compression of the batch on the batch's own streams, ordered after
  * the work already on `stream`; `stream` waits for the batch.  Results (and the
  * report) are valid after `stream` is synchronised.  Each job's arithmetic does not
  * depend on the other jobs, so its results equal those of blr_tag_compress on the

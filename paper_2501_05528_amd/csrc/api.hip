@@ -1623,6 +1623,10 @@ struct blr_batch {
     int grid = 512;
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    // per-job stages after the sketch run on a few lanes (streams) forked from and joined to own
+    std::vector<hipStream_t> lanes;
+    std::vector<hipEvent_t> lane_done;
+    hipEvent_t ev_fork = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~blr_batch() {
@@ -1634,8 +1638,13 @@ struct blr_batch {
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& j : jobs) delete j.handle;
         for (void* p : mem) (void)hipFree(p);
-        for (hipEvent_t e : {ev_in, ev_out, e0, e1, e2})
+        for (hipEvent_t e : {ev_in, ev_out, e0, e1, e2, ev_fork})
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+        for (hipStream_t l : lanes) {
+            (void)hipStreamSynchronize(l);
+            (void)hipStreamDestroy(l);
+        }
         if (own) (void)hipStreamDestroy(own);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
@@ -1668,6 +1677,8 @@ void batch_enqueue(blr_batch& B, bool time_sketch) {
         }
     }
     if (time_sketch) HIPC(hipEventRecord(B.e0, s));
+    // the persistent launches one after another: each fills the device (run side by side on
+    // the lanes they measured 17% slower)
     for (auto& c : B.classes) {
         if (c.precision == BLR_PREC_FP64)
             launch_sketch_multi(c.kind, c.ntr, c.spw[0], c.tg, c.d_jobs64, c.d_items[0], c.nitems[0], B.grid, s);
@@ -1676,25 +1687,35 @@ void batch_enqueue(blr_batch& B, bool time_sketch) {
                                    c.nitems[c.chosen], B.grid, s);
     }
     if (time_sketch) HIPC(hipEventRecord(B.e1, s));
-    for (auto& j : B.jobs) {
+    // the jobs' remaining stages are independent of each other (every job owns its buffers):
+    // job q runs on lane q mod lanes, so small jobs' launches overlap on the device
+    HIPC(hipEventRecord(B.ev_fork, s));
+    for (hipStream_t l : B.lanes) HIPC(hipStreamWaitEvent(l, B.ev_fork, 0));
+    for (size_t q = 0; q < B.jobs.size(); ++q) {
+        auto& j = B.jobs[q];
+        const hipStream_t ls = B.lanes[q % B.lanes.size()];
         const PlanData& P = *j.plan;
         const DeviceTables& t = *j.t;
         UblrData& h = *j.handle->d;
         if (is_mixed(j.precision)) {
-            launch_postprocess_lp(P, t, j.r_lo, j.Y0, j.Yh, s);
-            launch_postprocess_lp(P, t, j.r_lo, j.Z0, j.Zh, s);
-            launch_orth_cols(P, t, j.r_lo, j.r_lo, 1, j.Yh, j.Zh, j.U0, j.V0, nullptr, nullptr, s);
-            launch_mix(P, t, j.r_lo, j.V0, j.gamma_v, j.Xv, s);
-            launch_mix(P, t, j.r_lo, j.U0, j.gamma_u, j.Xu, s);
-            launch_refine(*j.op, P, t, j.Xv, j.Xu, j.SY, j.SZ, s);
-            launch_orth2(P, t, j.SY, j.SZ, h.U, h.V, nullptr, nullptr, s);
+            launch_postprocess_lp(P, t, j.r_lo, j.Y0, j.Yh, ls);
+            launch_postprocess_lp(P, t, j.r_lo, j.Z0, j.Zh, ls);
+            launch_orth_cols(P, t, j.r_lo, j.r_lo, 1, j.Yh, j.Zh, j.U0, j.V0, nullptr, nullptr, ls);
+            launch_mix(P, t, j.r_lo, j.V0, j.gamma_v, j.Xv, ls);
+            launch_mix(P, t, j.r_lo, j.U0, j.gamma_u, j.Xu, ls);
+            launch_refine(*j.op, P, t, j.Xv, j.Xu, j.SY, j.SZ, ls);
+            launch_orth2(P, t, j.SY, j.SZ, h.U, h.V, nullptr, nullptr, ls);
         } else {
-            launch_postprocess(P, t, j.Y, j.Yh, s);
-            launch_postprocess(P, t, j.Z, j.Zh, s);
-            launch_orth2(P, t, j.Yh, j.Zh, h.U, h.V, nullptr, nullptr, s);
+            launch_postprocess(P, t, j.Y, j.Yh, ls);
+            launch_postprocess(P, t, j.Z, j.Zh, ls);
+            launch_orth2(P, t, j.Yh, j.Zh, h.U, h.V, nullptr, nullptr, ls);
         }
-        launch_cores(*j.op, P, t, h.U, h.V, h.Atil, s);
-        launch_nearfield(*j.op, P, t, h.U, h.V, h.Atil, h.B, j.nfw, s);
+        launch_cores(*j.op, P, t, h.U, h.V, h.Atil, ls);
+        launch_nearfield(*j.op, P, t, h.U, h.V, h.Atil, h.B, j.nfw, ls);
+    }
+    for (size_t i = 0; i < B.lanes.size(); ++i) {
+        HIPC(hipEventRecord(B.lane_done[i], B.lanes[i]));
+        HIPC(hipStreamWaitEvent(s, B.lane_done[i], 0));
     }
 }
 
@@ -1945,6 +1966,16 @@ blr_status blr_batch_create(int32_t njobs, const blr_batch_job* jobs, int32_t fl
         }
         HIPC(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
         for (hipEvent_t* e : {&B->ev_in, &B->ev_out, &B->e0, &B->e1, &B->e2}) HIPC(hipEventCreate(e));
+        HIPC(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+        const int nlanes = std::min(4, njobs);
+        for (int i = 0; i < nlanes; ++i) {
+            hipStream_t l = nullptr;
+            HIPC(hipStreamCreateWithFlags(&l, hipStreamNonBlocking));
+            B->lanes.push_back(l);
+            hipEvent_t e = nullptr;
+            HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            B->lane_done.push_back(e);
+        }
         *out = B.release();
     });
 }
