@@ -188,16 +188,16 @@ struct KernelSrc {
     };
     __device__ P row(int64_t i) const { return P{px[i], py[i], pz[i], i}; }
     __device__ P col(int64_t j) const { return P{px[j], py[j], pz[j], j}; }
-    __device__ double val(const P& a, const P& b) const {
+    // entry between two different points (i != j)
+    __device__ double val_off(const P& a, const P& b) const {
         double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        double v;
         if constexpr (KIND == BLR_KERNEL_LOG)
-            v = 0.5 * log_tab(r2, ltab);
+            return 0.5 * log_tab(r2, ltab);
         else
-            v = kval<KIND>(r2);
-        return a.i == b.i ? diag : v;
+            return kval<KIND>(r2);
     }
+    __device__ double val(const P& a, const P& b) const { return a.i == b.i ? diag : val_off(a, b); }
     // column contexts staged through LDS: 3 doubles per column
     static constexpr int STAGE = 3;
     __device__ void stage(int64_t j, double* c) const {
@@ -224,6 +224,7 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ double val(const P& a, const P& b) const { return A[a.i + b.i * lda]; }
+    __device__ double val_off(const P& a, const P& b) const { return val(a, b); }
     static constexpr int STAGE = 1;
     __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
     __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
@@ -243,6 +244,7 @@ struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
     __device__ P row(int64_t i) const { return P{i}; }
     __device__ P col(int64_t j) const { return P{j}; }
     __device__ double val(const P& a, const P& b) const { return A[b.i + a.i * lda]; }
+    __device__ double val_off(const P& a, const P& b) const { return val(a, b); }
     static constexpr int STAGE = 1;
     __device__ void stage(int64_t, double* c) const { c[0] = 0.0; }
     __device__ P col_staged(const double*, int64_t j) const { return P{j}; }
@@ -711,8 +713,9 @@ __global__ __launch_bounds__(256, 2) void k_sketch(AS A, const double* __restric
 // FP64 exp and cos paths spill registers.  The tag columns are split evenly over the
 // groups, so a class can use one tag column per wave fewer than k_sketch when every job
 // allows it (for ell = 13 and 4 column tiles: 2 groups of 6 and 7 instead of 12 and 1, and
-// no spills).  Each tag column's sums run in the same order as in k_sketch, so a job's Y
-// and Z equal its single-job sketch bit for bit.
+// no spills).  TG is the last-tile form k_sketch takes for the class's kernel kind and r.
+// Each tag column's sums run in the same order as in k_sketch, so a job's Y and Z equal
+// its single-job sketch bit for bit.
 template <int KIND, int NTR, int SVW, int TG>
 __global__ __launch_bounds__(256, 2) void k_sketch_multi(const Fp64Job* __restrict__ jobs,
                                                          const int4* __restrict__ items, int nitems) {
@@ -1436,12 +1439,21 @@ __global__ __launch_bounds__(256, (NT >= 4 ? 1 : 2)) void k_cores(AS A, const in
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+        // a whole step of an off-diagonal pair needs neither the column bound nor the diagonal
+        // rule; rows past the box repeat its first point (finite entries, and their products
+        // meet zero rows of U and V below)
+        const bool offdiag = i != j;
         for (int k0 = 0; k0 < mj; k0 += KT) {
+            if (offdiag && k0 + KT <= mj) {
 #pragma unroll 4
-            for (int kk = 0; kk < KT; ++kk) {
-                double v = 0.0;
-                if (rowok && k0 + kk < mj) v = A.val(rp, A.col(cj0 + k0 + kk));
-                sA[kk * RC + tid] = v;
+                for (int kk = 0; kk < KT; ++kk) sA[kk * RC + tid] = A.val_off(rp, A.col(cj0 + k0 + kk));
+            } else {
+#pragma unroll 4
+                for (int kk = 0; kk < KT; ++kk) {
+                    double v = 0.0;
+                    if (rowok && k0 + kk < mj) v = A.val(rp, A.col(cj0 + k0 + kk));
+                    sA[kk * RC + tid] = v;
+                }
             }
             for (int idx = tid; idx < KT * KP; idx += 256) {
                 const int kk = idx / KP, c = idx - kk * KP;
@@ -1539,12 +1551,21 @@ __global__ __launch_bounds__(256, 2) void k_cores_sym(
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT2; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+        // a whole step of an off-diagonal pair needs neither the column bound nor the diagonal
+        // rule; rows past the box repeat its first point (finite entries, and their products
+        // meet zero rows of U and V below)
+        const bool offdiag = i != j;
         for (int k0 = 0; k0 < mj; k0 += KT) {
+            if (offdiag && k0 + KT <= mj) {
 #pragma unroll 4
-            for (int kk = 0; kk < KT; ++kk) {
-                double v = 0.0;
-                if (rowok && k0 + kk < mj) v = A.val(rp, A.col(cj0 + k0 + kk));
-                sA[kk * RC + tid] = v;
+                for (int kk = 0; kk < KT; ++kk) sA[kk * RC + tid] = A.val_off(rp, A.col(cj0 + k0 + kk));
+            } else {
+#pragma unroll 4
+                for (int kk = 0; kk < KT; ++kk) {
+                    double v = 0.0;
+                    if (rowok && k0 + kk < mj) v = A.val(rp, A.col(cj0 + k0 + kk));
+                    sA[kk * RC + tid] = v;
+                }
             }
             for (int idx = tid; idx < KT * 2 * KP; idx += 256) {
                 const int kk = idx / (2 * KP), cc = idx - kk * 2 * KP;
@@ -1687,6 +1708,7 @@ __global__ __launch_bounds__(256) void k_nf_b(
     __shared__ double scol[NB * CW * AS::STAGE];
     __shared__ int64_t sidx[NB * CW];
     __shared__ int svalid[NB * CW];
+    __shared__ int sfull[NB];          // box bq of the block: another box, all CW columns valid
     __shared__ double sQ[CW * KP];
     const int tid = threadIdx.x;
     const int pair = blockIdx.x;
@@ -1730,15 +1752,25 @@ __global__ __launch_bounds__(256) void k_nf_b(
                     A.stage(j, scol + e * AS::STAGE);
                     sidx[e] = j;
                     svalid[e] = ok ? 1 : 0;
+                    if (cc == 0) sfull[bq] = (lp != i && col0 + CW <= mlp) ? 1 : 0;
                 }
                 __syncthreads();
 #pragma unroll 1
                 for (int bq = 0; bq < nbq; ++bq) {
+                    if (__builtin_amdgcn_readfirstlane(sfull[bq])) {
+                        // another box and every column in it: no diagonal rule, no masking
 #pragma unroll
-                    for (int cc = 0; cc < CW; ++cc) {
-                        const int e = bq * CW + cc;
-                        const double v = A.val(rp, A.col_staged(scol + e * AS::STAGE, sidx[e]));
-                        acc[cc] += svalid[e] ? v : 0.0;
+                        for (int cc = 0; cc < CW; ++cc) {
+                            const int e = bq * CW + cc;
+                            acc[cc] += A.val_off(rp, A.col_staged(scol + e * AS::STAGE, sidx[e]));
+                        }
+                    } else {
+#pragma unroll
+                        for (int cc = 0; cc < CW; ++cc) {
+                            const int e = bq * CW + cc;
+                            const double v = A.val(rp, A.col_staged(scol + e * AS::STAGE, sidx[e]));
+                            acc[cc] += svalid[e] ? v : 0.0;
+                        }
                     }
                 }
             }
