@@ -211,6 +211,7 @@ struct KernelSrc {
     using Pre = P;
     __device__ Pre pre(const P&, int64_t j) const { return col(j); }
     __device__ double fin(const P& a, const Pre& b) const { return val(a, b); }
+    __device__ double fin_off(const P& a, const Pre& b) const { return val_off(a, b); }
 };
 
 struct DenseSrc {  // A(i, j) = A[i + j*lda]
@@ -231,6 +232,7 @@ struct DenseSrc {  // A(i, j) = A[i + j*lda]
     using Pre = double;
     __device__ Pre pre(const P& a, int64_t j) const { return A[a.i + j * lda]; }
     __device__ double fin(const P&, Pre v) const { return v; }
+    __device__ double fin_off(const P&, Pre v) const { return v; }
 };
 
 struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
@@ -251,6 +253,7 @@ struct DenseTSrc {  // (A*)(i, j) = A[j + i*lda]
     using Pre = double;
     __device__ Pre pre(const P& a, int64_t j) const { return A[j + a.i * lda]; }
     __device__ double fin(const P&, Pre v) const { return v; }
+    __device__ double fin_off(const P&, Pre v) const { return v; }
 };
 
 // ------------------------------------------------------------ B operands
@@ -942,11 +945,13 @@ __global__ __launch_bounds__(256, 2) void k_refine(AS A, const int64_t* __restri
             apre[u] = A.pre(rp, j < jend ? j : jend - 1);
         }
     };
+    // near blocks (the diagonal among them) are masked, so no entry needs the diagonal rule;
+    // a masked value is discarded by the select, never multiplied
     auto gen_a = [&](int buf, int64_t jb, int64_t jend) {
 #pragma unroll
         for (int u = 0; u < MA; ++u) {
             const int kk = akk + KSTEP * u;
-            const double v = A.fin(rp, apre[u]);
+            const double v = A.fin_off(rp, apre[u]);
             sA[buf][kk * BM + arow] = (far_pre && jb + kk < jend) ? v : 0.0;
         }
     };
