@@ -1834,8 +1834,24 @@ __global__ __launch_bounds__(256) void k_nf_q_m(const int64_t* __restrict__ box_
                 ? Atil[(static_cast<int64_t>(i) * k + t) + (static_cast<int64_t>(lp) * k + sx) * ldAt] : 0.0;
         }
         __syncthreads();
+        // V_lp operands are loaded one 4-deep slice ahead of the MFMAs that use them
+        auto load_v = [&](double* a, int s0) {
+            const int s2 = s0 + srow;
+#pragma unroll
+            for (int rr = 0; rr < RTW; ++rr) {
+                const int col = (wave + 4 * rr) * 16 + lcol;
+                a[rr] = (wave + 4 * rr < nrt && col < mlp && s2 < k)
+                    ? V[lp0 + col + static_cast<int64_t>(s2) * ldUV] : 0.0;
+            }
+        };
+        double an[RTW];
+        load_v(an, 0);
         for (int s0 = 0; s0 < k; s0 += 4) {
             const int s2 = s0 + srow;                    // < KP: KP is a multiple of 16 >= k
+            double a[RTW];
+#pragma unroll
+            for (int rr = 0; rr < RTW; ++rr) a[rr] = an[rr];
+            if (s0 + 4 < k) load_v(an, s0 + 4);
             double bb[NTT];
 #pragma unroll
             for (int nt = 0; nt < NTT; ++nt) bb[nt] = sAt[s2 * SP + nt * 16 + lcol];
@@ -1843,10 +1859,8 @@ __global__ __launch_bounds__(256) void k_nf_q_m(const int64_t* __restrict__ box_
             for (int rr = 0; rr < RTW; ++rr) {
                 const int rt = wave + 4 * rr;
                 if (rt >= nrt) continue;                 // uniform over the wave
-                const int col = rt * 16 + lcol;
-                const double a = (col < mlp && s2 < k) ? V[lp0 + col + static_cast<int64_t>(s2) * ldUV] : 0.0;
 #pragma unroll
-                for (int nt = 0; nt < NTT; ++nt) acc[rr][nt] = mfma64(a, bb[nt], acc[rr][nt]);
+                for (int nt = 0; nt < NTT; ++nt) acc[rr][nt] = mfma64(a[rr], bb[nt], acc[rr][nt]);
             }
         }
     }
