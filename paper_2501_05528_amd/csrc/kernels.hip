@@ -1781,7 +1781,7 @@ __global__ __launch_bounds__(256) void k_nf_b(
             }
             if (rowok) {
                 const double* ur = U + ri0 + arow;
-#pragma unroll 1
+#pragma unroll 8
                 for (int t = 0; t < k; ++t) {
                     const double u = ur[static_cast<int64_t>(t) * ldUV];
 #pragma unroll
